@@ -1,0 +1,142 @@
+"""Pins of the oracle's transform, magnitude and normalisation steps.
+
+Each check ties the oracle to something other than itself: an independent FP64
+FFT library, Parseval's identity, the closed-form spectrum of pure tones, and
+the quantisation-error bound of noiseless synthetic frames.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _rand_frames(rng, f, n, lim=8192):
+    return rng.integers(-lim, lim, size=(f, n)).astype(np.int16)
+
+
+@pytest.mark.parametrize("n", [8, 16, 512, 1024, 2048, 4096, 8192])
+def test_dft_matches_numpy_rfft(n):
+    rng = np.random.default_rng(n)
+    fr = _rand_frames(rng, 3, n)
+    bins = np.arange(n // 2 + 1) if n <= 512 else rng.choice(n // 2 + 1, 200, replace=False)
+    re, im = oracle.dft_at_bins(fr, bins)
+    ref = np.fft.rfft(fr.astype(np.float64), axis=1)[:, bins]
+    scale = np.abs(ref).max()
+    assert np.max(np.abs((re + 1j * im) - ref)) <= 1e-12 * scale * np.sqrt(n)
+
+
+@pytest.mark.parametrize("n", [16, 1024, 4096])
+def test_parseval(n):
+    rng = np.random.default_rng(1 + n)
+    fr = _rand_frames(rng, 1, n)
+    x = fr[0].astype(np.float64)
+    spec = oracle.full_dft(fr[0])
+    p = np.abs(spec) ** 2
+    lhs = float(x @ x)
+    rhs = (p[0] + 2.0 * p[1:n // 2].sum() + p[n // 2]) / n
+    assert abs(lhs - rhs) <= 1e-12 * lhs
+
+
+@pytest.mark.parametrize("k0", [1, 7, 100, 511])
+def test_pure_tone_placement(k0):
+    n = 1024
+    t = np.arange(n)
+    amp = 3000.0
+    for phase in (0.0, 0.3, 2.0):
+        x = amp * np.cos(2 * np.pi * k0 * t / n + phase)
+        # exact integers would quantise; use a frame whose float64 cast is exact by
+        # evaluating the transform on the int16-rounded tone and on the float tone bound
+        fr = np.rint(x).astype(np.int16)[None, :]
+        spec = oracle.full_dft(fr[0])
+        mag = np.abs(spec)
+        # rounding the tone to integers changes each bin by at most sum|e_t| <= N/2
+        assert abs(mag[k0] - amp * n / 2) <= n / 2
+        others = np.delete(mag, k0)
+        assert others.max() <= n / 2
+
+
+def test_dc_and_nyquist():
+    n = 64
+    dc = np.full((1, n), 1234, dtype=np.int16)
+    spec = oracle.full_dft(dc[0])
+    assert spec[0].real == pytest.approx(1234 * n, rel=1e-15)
+    assert np.abs(spec[1:]).max() <= 1e-9 * 1234 * n
+    ny = (1000 * (-1) ** np.arange(n)).astype(np.int16)
+    spec = oracle.full_dft(ny)
+    assert abs(spec[n // 2]) == pytest.approx(1000 * n, rel=1e-15)
+    assert np.abs(spec[: n // 2]).max() <= 1e-9 * 1000 * n
+
+
+def test_linearity_and_int16_extremes():
+    rng = np.random.default_rng(5)
+    n = 256
+    bins = np.arange(1, 100)
+    a = _rand_frames(rng, 1, n, 10000)
+    b = _rand_frames(rng, 1, n, 10000)
+    ra, ia = oracle.dft_at_bins(a, bins)
+    rb, ib = oracle.dft_at_bins(b, bins)
+    rs, is_ = oracle.dft_at_bins((a.astype(np.int32) + b).astype(np.int16), bins)
+    assert np.allclose(rs, ra + rb, atol=1e-8) and np.allclose(is_, ia + ib, atol=1e-8)
+    ext = np.where(np.arange(n) % 3 == 0, -32768, 32767).astype(np.int16)[None, :]
+    re, im = oracle.dft_at_bins(ext, np.arange(n // 2 + 1))
+    ref = np.fft.rfft(ext.astype(np.float64), axis=1)
+    assert np.max(np.abs(re + 1j * im - ref)) <= 1e-9 * np.abs(ref).max()
+    zero = np.zeros((2, n), dtype=np.int16)
+    assert np.all(oracle.tooth_magnitudes(zero, bins) == 0.0)
+
+
+def test_rejects_non_int16():
+    with pytest.raises(TypeError):
+        oracle.dft_at_bins(np.zeros((1, 8), dtype=np.int32), [1])
+
+
+def test_noiseless_teeth_amplitudes_closed_form():
+    """A noiseless quantised frame holds tooth amplitudes g A_i N/2 up to the
+    quantisation error, whose per-bin standard deviation is sqrt(N/24) in each
+    of Re and Im (uniform rounding error of variance 1/12 per sample)."""
+    spec = synth.spec_tiny()
+    bt = synth.make_batch(spec, 8, seed=3, noise=False)
+    m = oracle.tooth_magnitudes(bt.frames, spec.bins)
+    i = np.arange(spec.k)
+    u = 2.0 * (i[None, :] - bt.centre[:, None]) / bt.width[:, None]
+    amp = bt.baseline[:, None] * (1.0 - bt.depth[:, None] / (1.0 + u * u))
+    expect = bt.gain * amp * spec.n / 2
+    sd = np.sqrt(spec.n / 24.0)
+    assert np.max(np.abs(m - expect)) <= 6.0 * sd
+    ref = oracle.reference_spectrum(bt.ref_frames, spec.bins)
+    assert np.max(np.abs(ref - bt.gain * spec.n / 2)) <= 6.0 * sd
+    y = oracle.normalize(m, ref)
+    assert np.max(np.abs(y - amp)) <= 2e-3
+
+
+def test_normalize_rejects_bad_reference():
+    with pytest.raises(ValueError):
+        oracle.normalize(np.ones((2, 3)), np.array([1.0, 0.0, 1.0]))
+    with pytest.raises(ValueError):
+        oracle.normalize(np.ones((2, 3)), np.array([1.0, np.nan, 1.0]))
+
+
+def test_paper_geometry_fixture():
+    """The tiny workload's geometry follows the paper's printed numbers: beat
+    tones at the 51 MHz offset plus multiples of the 10 MHz comb spacing, and a
+    cavity linewidth FSR/finesse of about 8 teeth."""
+    g = json.load(open(os.path.join(HERE, "golden", "paper_geometry.json")))
+    c = g["speed_of_light_m_s"]["value"]
+    fsr = c / (2.0 * g["cavity_length_m"]["value"])
+    linewidth = fsr / g["cavity_finesse"]["value"]
+    teeth = linewidth / g["comb_spacing_hz"]["value"]
+    assert 7.9 < teeth < 8.1
+    assert synth.spec_tiny().width == (8.0, 8.0)
+    bin_hz = 1.024e9 / 1024
+    n = np.arange(-55, 45)
+    beat = np.abs(g["lo_shift_hz"]["value"] + g["comb_spacing_hz"]["value"] * n)
+    assert np.array_equal(synth.tooth_bins_paper_c1(), (beat / bin_hz).astype(np.int32))
+    span = 100 * g["comb_spacing_hz"]["value"]
+    assert span <= g["comb_span_hz"]["value"]
