@@ -1,0 +1,225 @@
+/*
+ * combgpu.h -- C ABI of the MI355X (gfx950) comb-spectroscopy hot path.
+ *
+ * Method (paper, "Data Capture and Processing"): raw integer digitizer samples
+ * are cast to floating point, cut into frames of consecutive samples, each
+ * frame is Fourier transformed, the bins of the comb teeth are picked out in
+ * optical order, each spectrum is divided by an averaged reference spectrum,
+ * a 7x7 median filter over the (frame, tooth) image gives the starting centre,
+ * and a Levenberg-Marquardt fit of the cavity resonance returns its centre
+ * (the proof-mass displacement proxy) per frame.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns a cg_status; nothing throws or aborts across the
+ *   ABI.  CG_ERR_HIP carries a thread-local detail string, see
+ *   cg_last_error_detail().
+ * - "device" pointers are HIP device allocations (e.g. torch tensors on the
+ *   GPU); "host" pointers are ordinary CPU memory.  The caller owns every
+ *   buffer it passes in and keeps device buffers alive until the stream work
+ *   has completed.
+ * - `stream` is a hipStream_t passed as void*; NULL selects the plan's own
+ *   stream.  Work is only enqueued: the call returns before the GPU finishes.
+ * - Arrays are row-major and contiguous: frames int16 [n_frames][frame_len];
+ *   spectra float32 [n_frames][n_teeth]; parameters float32 [n_frames][4] in
+ *   the order (centre, width, depth, baseline).
+ * - Centre and width are in units of the tooth index (0 .. n_teeth-1, optical
+ *   order); width is the full width at half depth of the Lorentzian dip
+ *   y(x) = baseline * (1 - depth / (1 + (2 (x - centre) / width)^2)).
+ * - n_frames == 0 is a no-op returning CG_OK; n_frames < 0 is
+ *   CG_ERR_INVALID_ARG.
+ * - A plan may be used from one host thread at a time.
+ */
+#ifndef COMBGPU_H
+#define COMBGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cg_plan cg_plan;
+typedef int32_t cg_status;
+
+/* Return codes. */
+#define CG_OK               0
+#define CG_ERR_INVALID_ARG (-1) /* a size, count or flag is out of range        */
+#define CG_ERR_UNSUPPORTED (-2) /* frame_len or n_teeth outside what is built   */
+#define CG_ERR_BAD_REF     (-3) /* reference spectrum not finite and > 0        */
+#define CG_ERR_NULL        (-4) /* a required pointer is NULL                   */
+#define CG_ERR_OOM         (-5) /* device allocation failed                     */
+#define CG_ERR_HIP         (-6) /* HIP runtime / launch error (see detail)      */
+#define CG_ERR_WORKSPACE   (-7) /* caller workspace smaller than required       */
+#define CG_ERR_STATE       (-8) /* operation needs state the plan lacks         */
+
+/* Per-frame fit status written to out_status. */
+#define CG_FIT_CONVERGED 0 /* accepted step lowered chi2 by <= 1e-6 chi2        */
+#define CG_FIT_MAX_ITER  1 /* iteration cap reached; last accepted point kept  */
+#define CG_FIT_SINGULAR  2 /* damped normal matrix not positive definite       */
+#define CG_FIT_FALLBACK  3 /* warm start rejected, cold-start fit used         */
+
+/* Flags of cg_process_batch_ex: one DFT form ... */
+#define CG_DFT_FFT         0x0u /* FP32 real FFT (default)                       */
+#define CG_DFT_MFMA_BF16X3 0x1u /* tooth DFT on BF16 MFMA, hi/lo split, 3 terms  */
+#define CG_DFT_MFMA_FP16   0x2u /* tooth DFT on FP16 MFMA, one term              */
+#define CG_DFT_MFMA_FP16X2 0x3u /* tooth DFT on FP16 MFMA, split samples, 2 terms*/
+#define CG_DFT_MASK        0xFu
+/* ... and one start-point form. */
+#define CG_FIT_COLD      0x00u /* 7x7 median start point, full LM (default)     */
+#define CG_FIT_WARM_MLP  0x10u /* learned warm start + 2-iteration polish       */
+#define CG_FIT_NONE      0x20u /* stop after the normalised spectra             */
+#define CG_FIT_MASK      0xF0u
+
+/* Supported sizes. */
+#define CG_MIN_FRAME_LEN 512
+#define CG_MAX_FRAME_LEN 8192
+#define CG_MAX_TEETH     440
+#define CG_MAX_ITER      64
+
+/*
+ * Create a plan for frames of `frame_len` samples (a power of two in
+ * 512..8192) and `n_teeth` comb teeth (1..min(440, frame_len/2+1)).
+ *   fs            sample rate in Hz (> 0, finite); metadata only: bin k is
+ *                 k*fs/frame_len Hz and frame f starts at f*frame_len/fs s.
+ *   tooth_bins    host int32[n_teeth]: DFT bin of each tooth in optical
+ *                 order; each in [0, frame_len/2], all distinct.
+ *   ref_spectrum  host float32[n_teeth]: averaged reference amplitudes in the
+ *                 units of |X[k]| of the unnormalised forward DFT of the raw
+ *                 int16 frame; finite and > 0 (paper: average reference
+ *                 spectrum recorded at the start of the experiment).
+ *   out_plan      receives the plan; set to NULL on failure.
+ * Arguments are validated on the host before any HIP call.  The plan owns its
+ * device tables and a stream; release it with cg_destroy_plan.
+ * Errors: CG_ERR_NULL, CG_ERR_UNSUPPORTED, CG_ERR_INVALID_ARG, CG_ERR_BAD_REF,
+ * CG_ERR_OOM, CG_ERR_HIP.
+ */
+cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins,
+                         int32_t n_teeth, const float* ref_spectrum, cg_plan** out_plan);
+
+/* Release a plan and everything it owns (NULL is allowed).  Synchronises the
+ * plan's stream first. */
+cg_status cg_destroy_plan(cg_plan* plan);
+
+/* Replace the plan's reference spectrum (host float32[n_teeth], finite, > 0). */
+cg_status cg_set_reference(cg_plan* plan, const float* ref_spectrum);
+
+/* Read back the plan's geometry (any output pointer may be NULL). */
+cg_status cg_plan_info(const cg_plan* plan, int32_t* frame_len, int32_t* n_teeth, double* fs);
+
+/*
+ * Bytes of device workspace cg_process_batch_ex needs for `n_frames` frames
+ * when the caller supplies one: two float32 [n_frames][n_teeth] images (the
+ * normalised spectra and their 7x7 median) and the float32 [n_frames][4]
+ * start points, each 256-byte aligned.  The workspace must be 256-byte
+ * aligned.
+ */
+cg_status cg_workspace_bytes(const cg_plan* plan, int64_t n_frames, size_t* bytes);
+
+/*
+ * Whole hot path for one batch: cast + frame, real FFT, tooth gather,
+ * amplitude, division by the reference, 7x7 median start point and the
+ * Levenberg-Marquardt fit (at most 20 iterations, tolerance 1e-6).
+ *   frames      device int16[n_frames][frame_len].
+ *   out_params  device float32[n_frames][4] (centre, width, depth, baseline).
+ * Uses the plan's internal workspace, grown on demand (the first call for a
+ * larger batch allocates).  The 7x7 median window replicates the first and
+ * last frame of the batch at its edges, so results depend on how a stream is
+ * cut into batches only within three frames of a cut.
+ */
+cg_status cg_process_batch(cg_plan* plan, const int16_t* frames, int64_t n_frames,
+                           float* out_params, void* stream);
+
+/*
+ * As cg_process_batch, with optional outputs (each NULL = not written):
+ *   out_iters   device int32[n_frames]  LM iterations used.
+ *   out_status  device int32[n_frames]  CG_FIT_* code.
+ *   out_chi2    device float32[n_frames] final sum of squared residuals.
+ *   out_teeth   device float32[n_frames][n_teeth] raw amplitudes |X[k_i]|.
+ *   out_y       device float32[n_frames][n_teeth] normalised spectra.
+ *   flags       one CG_DFT_* form OR one CG_FIT_* form.
+ *   workspace   device buffer of >= cg_workspace_bytes() bytes, or NULL to use
+ *               the plan's own (then workspace_bytes is ignored).
+ * out_params may be NULL only with CG_FIT_NONE.
+ * Errors: CG_ERR_WORKSPACE if workspace_bytes is too small; CG_ERR_STATE for
+ * CG_FIT_WARM_MLP before cg_set_mlp; CG_ERR_INVALID_ARG for unknown flags.
+ */
+cg_status cg_process_batch_ex(cg_plan* plan, const int16_t* frames, int64_t n_frames,
+                              float* out_params, int32_t* out_iters, int32_t* out_status,
+                              float* out_chi2, float* out_teeth, float* out_y, uint32_t flags,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Transform stage only: amplitudes at the tooth bins and/or normalised
+ * spectra (either output may be NULL, not both).  `flags` selects the DFT form
+ * (CG_DFT_*).  frames device int16[n_frames][frame_len]; outputs device
+ * float32[n_frames][n_teeth].
+ */
+cg_status cg_teeth(cg_plan* plan, const int16_t* frames, int64_t n_frames, float* out_teeth,
+                   float* out_y, uint32_t flags, void* stream);
+
+/*
+ * Averaged reference spectrum (paper: pre-calculated average reference
+ * spectrum): out_ref[i] = mean over the n reference frames of |X[k_i]|,
+ * accumulated in FP64 in frame order.  ref_frames device int16[n][frame_len];
+ * out_ref device float32[n_teeth].  The plan's own reference is not changed;
+ * copy the result to the host and pass it to cg_set_reference to install it.
+ */
+cg_status cg_reference_from_frames(cg_plan* plan, const int16_t* ref_frames, int64_t n,
+                                   float* out_ref, void* stream);
+
+/*
+ * Cold-start initial guess on normalised spectra y (device float32
+ * [n_frames][n_teeth]): M = 7x7 median of y over (frame, tooth) with edge
+ * replication inside the batch; per frame centre = first index of min M,
+ * baseline = lower median of the row of M, depth = clip(1 - M[centre] /
+ * baseline, 0.05, 0.95) (0.05 if baseline <= 0), width = max(2, count of teeth
+ * with M < baseline (1 - depth/2)), all decisions in float32.
+ *   out_p0      device float32[n_frames][4].
+ *   out_median  device float32[n_frames][n_teeth] or NULL.
+ * Needs a workspace for M when out_median is NULL (the plan's own is used).
+ */
+cg_status cg_init_spectra(cg_plan* plan, const float* y, int64_t n_frames, float* out_p0,
+                          float* out_median, void* stream);
+
+/*
+ * The two kernels of cg_init_spectra, callable on their own:
+ * cg_median_filter writes out_median = 7x7 median image of y (both device
+ * float32 [n_frames][n_teeth], distinct buffers); cg_start_points turns a
+ * median image into start points out_p0 (device float32 [n_frames][4]) by the
+ * rules of cg_init_spectra.
+ */
+cg_status cg_median_filter(cg_plan* plan, const float* y, int64_t n_frames, float* out_median,
+                           void* stream);
+cg_status cg_start_points(cg_plan* plan, const float* median, int64_t n_frames, float* out_p0,
+                          void* stream);
+
+/*
+ * Levenberg-Marquardt fit of the Lorentzian dip to each row of y from p0
+ * (device float32 [n_frames][n_teeth] and [n_frames][4]).  Damped normal
+ * equations (A + lam diag A) d = J^T r solved by an FP64 Cholesky; lam starts
+ * at 1e-3, /10 on accept, *10 on reject; a step is accepted when chi2 does not
+ * increase, width stays > 0 and all values are finite; converged when an
+ * accepted step lowers chi2 by <= 1e-6 chi2 (or chi2 <= 1e-30).  max_iter in
+ * 1..CG_MAX_ITER (the paper uses 20).  Outputs as in cg_process_batch_ex.
+ */
+cg_status cg_fit_spectra(cg_plan* plan, const float* y, const float* p0, int64_t n_frames,
+                         int32_t max_iter, float* out_params, int32_t* out_iters,
+                         int32_t* out_status, float* out_chi2, void* stream);
+
+/* Static description of a status code. */
+const char* cg_status_string(cg_status status);
+
+/* Thread-local detail of the last CG_ERR_HIP / CG_ERR_OOM raised on this
+ * thread ("" if none). */
+const char* cg_last_error_detail(void);
+
+/* Library version string. */
+const char* cg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COMBGPU_H */

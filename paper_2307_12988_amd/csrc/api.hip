@@ -1,0 +1,366 @@
+// Host side of the C ABI declared in include/combgpu.h: argument validation
+// (before any HIP call), plan lifetime, workspace and kernel sequencing.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_set>
+
+#include "internal.h"
+
+namespace cg {
+
+namespace {
+thread_local std::string g_detail;
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t image_bytes(int64_t nf, int k) { return align256((size_t)nf * (size_t)k * sizeof(float)); }
+
+// workspace layout: y image | median image | start points [nf][4]
+size_t ws_bytes(int64_t nf, int k) {
+  return 2 * image_bytes(nf, k) + align256((size_t)nf * 4 * sizeof(float));
+}
+
+bool is_pow2(int32_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+cg_status check_geometry(int32_t n, double fs, const int32_t* bins, int32_t k) {
+  if (!bins) return CG_ERR_NULL;
+  if (!is_pow2(n) || n < CG_MIN_FRAME_LEN || n > CG_MAX_FRAME_LEN) {
+    set_detail("frame_len must be a power of two in [512, 8192]");
+    return CG_ERR_UNSUPPORTED;
+  }
+  if (k < 1) {
+    set_detail("n_teeth must be >= 1");
+    return CG_ERR_INVALID_ARG;
+  }
+  if (k > CG_MAX_TEETH || k > n / 2 + 1) {
+    set_detail("n_teeth exceeds min(440, frame_len/2+1)");
+    return CG_ERR_UNSUPPORTED;
+  }
+  if (!(fs > 0.0) || !std::isfinite(fs)) {
+    set_detail("fs must be finite and > 0");
+    return CG_ERR_INVALID_ARG;
+  }
+  std::unordered_set<int32_t> seen;
+  for (int32_t i = 0; i < k; ++i) {
+    if (bins[i] < 0 || bins[i] > n / 2) {
+      set_detail("tooth bin outside [0, frame_len/2]");
+      return CG_ERR_INVALID_ARG;
+    }
+    if (!seen.insert(bins[i]).second) {
+      set_detail("duplicate tooth bin");
+      return CG_ERR_INVALID_ARG;
+    }
+  }
+  return CG_OK;
+}
+
+cg_status check_ref(const float* ref, int32_t k) {
+  if (!ref) return CG_ERR_NULL;
+  for (int32_t i = 0; i < k; ++i) {
+    if (!std::isfinite(ref[i]) || !(ref[i] > 0.0f)) {
+      set_detail("reference spectrum must be finite and > 0");
+      return CG_ERR_BAD_REF;
+    }
+  }
+  return CG_OK;
+}
+
+hipStream_t pick(const cg_plan* p, void* s) {
+  return s ? reinterpret_cast<hipStream_t>(s) : p->stream;
+}
+
+bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
+
+// Grow the plan-owned workspace to at least `bytes`.
+cg_status ensure_ws(cg_plan* p, size_t bytes) {
+  if (bytes <= p->ws_bytes) return CG_OK;
+  hipError_t e = hipDeviceSynchronize();  // the old buffer may still be in use
+  if (e != hipSuccess) return hip_fail(e, "workspace grow: sync");
+  if (p->ws) (void)hipFree(p->ws);
+  p->ws = nullptr;
+  p->ws_bytes = 0;
+  e = hipMalloc(&p->ws, bytes);
+  if (e != hipSuccess) return hip_fail(e, "workspace grow: hipMalloc");
+  p->ws_bytes = bytes;
+  return CG_OK;
+}
+
+void free_plan(cg_plan* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  if (p->d_bins) (void)hipFree(p->d_bins);
+  if (p->d_ref) (void)hipFree(p->d_ref);
+  if (p->d_tw) (void)hipFree(p->d_tw);
+  if (p->ws) (void)hipFree(p->ws);
+  if (p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+}  // namespace
+
+void set_detail(const std::string& s) { g_detail = s; }
+
+cg_status hip_fail(hipError_t e, const char* where) {
+  set_detail(std::string(where) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? CG_ERR_OOM : CG_ERR_HIP;
+}
+
+}  // namespace cg
+
+using cg::hip_fail;
+
+extern "C" {
+
+const char* cg_status_string(cg_status s) {
+  switch (s) {
+    case CG_OK: return "ok";
+    case CG_ERR_INVALID_ARG: return "invalid argument";
+    case CG_ERR_UNSUPPORTED: return "unsupported frame length or tooth count";
+    case CG_ERR_BAD_REF: return "reference spectrum must be finite and > 0";
+    case CG_ERR_NULL: return "required pointer is NULL";
+    case CG_ERR_OOM: return "device allocation failed";
+    case CG_ERR_HIP: return "HIP runtime error";
+    case CG_ERR_WORKSPACE: return "workspace too small";
+    case CG_ERR_STATE: return "plan lacks the state this operation needs";
+    default: return "unknown status";
+  }
+}
+
+const char* cg_last_error_detail(void) { return cg::g_detail.c_str(); }
+
+const char* cg_version(void) { return "combgpu-mi355x 0.1.0 gfx950"; }
+
+cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins,
+                         int32_t n_teeth, const float* ref_spectrum, cg_plan** out_plan) {
+  if (!out_plan) return CG_ERR_NULL;
+  *out_plan = nullptr;
+  cg_status st = cg::check_geometry(frame_len, fs, tooth_bins, n_teeth);
+  if (st != CG_OK) return st;
+  st = cg::check_ref(ref_spectrum, n_teeth);
+  if (st != CG_OK) return st;
+
+  cg_plan* p = new (std::nothrow) cg_plan();
+  if (!p) return CG_ERR_OOM;
+  p->n = frame_len;
+  p->m = frame_len / 2;
+  p->k = n_teeth;
+  p->fs = fs;
+  p->h_bins.assign(tooth_bins, tooth_bins + n_teeth);
+  p->h_ref.assign(ref_spectrum, ref_spectrum + n_teeth);
+
+  // twiddles W_N^e built in FP64 and rounded once
+  std::vector<float2> tw(frame_len);
+  for (int32_t e = 0; e < frame_len; ++e) {
+    const double a = 2.0 * (double)e / (double)frame_len;  // angle / pi, exact
+    tw[e].x = (float)std::cos(M_PI * a);
+    tw[e].y = (float)-std::sin(M_PI * a);
+  }
+  hipError_t e;
+#define CG_TRY(call, what)                 \
+  do {                                      \
+    e = (call);                             \
+    if (e != hipSuccess) {                  \
+      st = hip_fail(e, what);               \
+      cg::free_plan(p);                     \
+      return st;                            \
+    }                                       \
+  } while (0)
+  CG_TRY(hipGetDevice(&p->device), "hipGetDevice");
+  CG_TRY(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking), "hipStreamCreate");
+  CG_TRY(hipMalloc(&p->d_bins, sizeof(int32_t) * n_teeth), "hipMalloc bins");
+  CG_TRY(hipMalloc(&p->d_ref, sizeof(float) * n_teeth), "hipMalloc ref");
+  CG_TRY(hipMalloc(&p->d_tw, sizeof(float2) * frame_len), "hipMalloc twiddles");
+  CG_TRY(hipMemcpy(p->d_bins, tooth_bins, sizeof(int32_t) * n_teeth, hipMemcpyHostToDevice),
+         "copy bins");
+  CG_TRY(hipMemcpy(p->d_ref, ref_spectrum, sizeof(float) * n_teeth, hipMemcpyHostToDevice),
+         "copy ref");
+  CG_TRY(hipMemcpy(p->d_tw, tw.data(), sizeof(float2) * frame_len, hipMemcpyHostToDevice),
+         "copy twiddles");
+#undef CG_TRY
+  *out_plan = p;
+  return CG_OK;
+}
+
+cg_status cg_destroy_plan(cg_plan* p) {
+  cg::free_plan(p);
+  return CG_OK;
+}
+
+cg_status cg_set_reference(cg_plan* p, const float* ref) {
+  if (!p) return CG_ERR_NULL;
+  cg_status st = cg::check_ref(ref, p->k);
+  if (st != CG_OK) return st;
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(p->d_ref, ref, sizeof(float) * p->k, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "cg_set_reference");
+  p->h_ref.assign(ref, ref + p->k);
+  return CG_OK;
+}
+
+cg_status cg_plan_info(const cg_plan* p, int32_t* frame_len, int32_t* n_teeth, double* fs) {
+  if (!p) return CG_ERR_NULL;
+  if (frame_len) *frame_len = p->n;
+  if (n_teeth) *n_teeth = p->k;
+  if (fs) *fs = p->fs;
+  return CG_OK;
+}
+
+cg_status cg_workspace_bytes(const cg_plan* p, int64_t n_frames, size_t* bytes) {
+  if (!p || !bytes) return CG_ERR_NULL;
+  if (n_frames < 0) return CG_ERR_INVALID_ARG;
+  *bytes = cg::ws_bytes(n_frames, p->k);
+  return CG_OK;
+}
+
+cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, float* out_params,
+                              int32_t* out_iters, int32_t* out_status, float* out_chi2,
+                              float* out_teeth, float* out_y, uint32_t flags, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  if (!p) return CG_ERR_NULL;
+  if (nf < 0) return CG_ERR_INVALID_ARG;
+  if ((flags & ~(CG_DFT_MASK | CG_FIT_MASK)) != 0u) return CG_ERR_INVALID_ARG;
+  const uint32_t dft = flags & CG_DFT_MASK;
+  const uint32_t fit = flags & CG_FIT_MASK;
+  if (dft > CG_DFT_MFMA_FP16X2) return CG_ERR_INVALID_ARG;
+  if (fit != CG_FIT_COLD && fit != CG_FIT_WARM_MLP && fit != CG_FIT_NONE)
+    return CG_ERR_INVALID_ARG;
+  if (nf == 0) return CG_OK;
+  if (fit != CG_FIT_NONE && !out_params) return CG_ERR_NULL;
+  if (fit == CG_FIT_NONE && !out_teeth && !out_y) return CG_ERR_NULL;
+  if (!frames) return CG_ERR_NULL;
+  if (!cg::aligned(frames, 4)) {
+    cg::set_detail("frames must be 4-byte aligned");
+    return CG_ERR_INVALID_ARG;
+  }
+  if (dft != CG_DFT_FFT) {
+    cg::set_detail("MFMA tooth-DFT forms are not built in this library version");
+    return CG_ERR_UNSUPPORTED;
+  }
+  if (fit == CG_FIT_WARM_MLP) {
+    cg::set_detail("learned warm start not available");
+    return CG_ERR_STATE;
+  }
+  const hipStream_t s = cg::pick(p, stream);
+  const size_t img = cg::image_bytes(nf, p->k);
+  const size_t need = cg::ws_bytes(nf, p->k);
+  char* ws;
+  if (workspace) {
+    if (workspace_bytes < need) return CG_ERR_WORKSPACE;
+    if (!cg::aligned(workspace, 256)) {
+      cg::set_detail("workspace must be 256-byte aligned");
+      return CG_ERR_INVALID_ARG;
+    }
+    ws = static_cast<char*>(workspace);
+  } else {
+    cg_status st = cg::ensure_ws(p, need);
+    if (st != CG_OK) return st;
+    ws = static_cast<char*>(p->ws);
+  }
+  float* y = out_y ? out_y : reinterpret_cast<float*>(ws);
+  float* m = reinterpret_cast<float*>(ws + img);
+  float* p0 = reinterpret_cast<float*>(ws + 2 * img);
+  hipError_t e = cg::launch_fft_teeth(p, frames, nf, out_teeth, y, s);
+  if (e != hipSuccess) return hip_fail(e, "fft_teeth launch");
+  if (fit == CG_FIT_NONE) return CG_OK;
+  e = cg::launch_median7(y, nf, p->k, m, s);
+  if (e != hipSuccess) return hip_fail(e, "median7 launch");
+  e = cg::launch_init_from_median(m, nf, p->k, p0, s);
+  if (e != hipSuccess) return hip_fail(e, "init launch");
+  e = cg::launch_lm(y, nullptr, p0, nf, p->k, 20, out_params, out_iters, out_status, out_chi2, s);
+  if (e != hipSuccess) return hip_fail(e, "lm launch");
+  return CG_OK;
+}
+
+cg_status cg_process_batch(cg_plan* p, const int16_t* frames, int64_t nf, float* out_params,
+                           void* stream) {
+  return cg_process_batch_ex(p, frames, nf, out_params, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, CG_DFT_FFT | CG_FIT_COLD, nullptr, 0, stream);
+}
+
+cg_status cg_teeth(cg_plan* p, const int16_t* frames, int64_t nf, float* out_teeth, float* out_y,
+                   uint32_t flags, void* stream) {
+  if (!p) return CG_ERR_NULL;
+  if ((flags & ~CG_DFT_MASK) != 0u || flags > CG_DFT_MFMA_FP16X2) return CG_ERR_INVALID_ARG;
+  return cg_process_batch_ex(p, frames, nf, nullptr, nullptr, nullptr, nullptr, out_teeth, out_y,
+                             flags | CG_FIT_NONE, nullptr, 0, stream);
+}
+
+cg_status cg_reference_from_frames(cg_plan* p, const int16_t* ref_frames, int64_t n,
+                                   float* out_ref, void* stream) {
+  if (!p || !out_ref) return CG_ERR_NULL;
+  if (n <= 0) return CG_ERR_INVALID_ARG;
+  if (!ref_frames) return CG_ERR_NULL;
+  if (!cg::aligned(ref_frames, 4)) return CG_ERR_INVALID_ARG;
+  const hipStream_t s = cg::pick(p, stream);
+  float* mags = nullptr;
+  hipError_t e = hipMalloc(&mags, (size_t)n * p->k * sizeof(float));
+  if (e != hipSuccess) return hip_fail(e, "reference: hipMalloc");
+  e = cg::launch_fft_teeth(p, ref_frames, n, mags, nullptr, s);
+  if (e == hipSuccess) e = cg::launch_column_mean(mags, n, p->k, out_ref, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(mags);
+  if (e != hipSuccess) return hip_fail(e, "reference");
+  return CG_OK;
+}
+
+cg_status cg_init_spectra(cg_plan* p, const float* y, int64_t nf, float* out_p0, float* out_median,
+                          void* stream) {
+  if (!p || !out_p0) return CG_ERR_NULL;
+  if (nf < 0) return CG_ERR_INVALID_ARG;
+  if (nf == 0) return CG_OK;
+  if (!y) return CG_ERR_NULL;
+  const hipStream_t s = cg::pick(p, stream);
+  float* m = out_median;
+  if (!m) {
+    cg_status st = cg::ensure_ws(p, cg::ws_bytes(nf, p->k));
+    if (st != CG_OK) return st;
+    m = reinterpret_cast<float*>(static_cast<char*>(p->ws) + cg::image_bytes(nf, p->k));
+  }
+  hipError_t e = cg::launch_median7(y, nf, p->k, m, s);
+  if (e == hipSuccess) e = cg::launch_init_from_median(m, nf, p->k, out_p0, s);
+  if (e != hipSuccess) return hip_fail(e, "init launch");
+  return CG_OK;
+}
+
+cg_status cg_median_filter(cg_plan* p, const float* y, int64_t nf, float* out_median,
+                           void* stream) {
+  if (!p || !out_median) return CG_ERR_NULL;
+  if (nf < 0) return CG_ERR_INVALID_ARG;
+  if (nf == 0) return CG_OK;
+  if (!y) return CG_ERR_NULL;
+  if (y == out_median) return CG_ERR_INVALID_ARG;
+  hipError_t e = cg::launch_median7(y, nf, p->k, out_median, cg::pick(p, stream));
+  if (e != hipSuccess) return hip_fail(e, "median launch");
+  return CG_OK;
+}
+
+cg_status cg_start_points(cg_plan* p, const float* median, int64_t nf, float* out_p0,
+                          void* stream) {
+  if (!p || !out_p0) return CG_ERR_NULL;
+  if (nf < 0) return CG_ERR_INVALID_ARG;
+  if (nf == 0) return CG_OK;
+  if (!median) return CG_ERR_NULL;
+  hipError_t e = cg::launch_init_from_median(median, nf, p->k, out_p0, cg::pick(p, stream));
+  if (e != hipSuccess) return hip_fail(e, "start point launch");
+  return CG_OK;
+}
+
+cg_status cg_fit_spectra(cg_plan* p, const float* y, const float* p0, int64_t nf, int32_t max_iter,
+                         float* out_params, int32_t* out_iters, int32_t* out_status,
+                         float* out_chi2, void* stream) {
+  if (!p || !out_params) return CG_ERR_NULL;
+  if (nf < 0 || max_iter < 1 || max_iter > CG_MAX_ITER) return CG_ERR_INVALID_ARG;
+  if (nf == 0) return CG_OK;
+  if (!y || !p0) return CG_ERR_NULL;
+  const hipStream_t s = cg::pick(p, stream);
+  hipError_t e = cg::launch_lm(y, nullptr, p0, nf, p->k, max_iter, out_params, out_iters,
+                               out_status, out_chi2, s);
+  if (e != hipSuccess) return hip_fail(e, "lm launch");
+  return CG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,289 @@
+// Ingest + real FFT + tooth gather + amplitude + division by the reference.
+//
+// Paper, Data Capture and Processing: integer samples are cast to single
+// precision on the GPU, reshaped into one frame per row, every row is Fourier
+// transformed, the bins of the comb teeth are selected in optical order and
+// divided by the averaged reference spectrum.
+//
+// gfx950 design
+// -------------
+// * A real frame of N samples is read as N/2 complex points z[t] = x[2t] +
+//   i x[2t+1] (one 32-bit load carries both int16 samples), transformed by a
+//   complex FFT of M = N/2 points, and the tooth bins are untangled from Z:
+//     X[k] = (Z[k] + conj Z[M-k]) / 2 - i W_N^k (Z[k] - conj Z[M-k]) / 2.
+//   Only the K tooth bins are untangled; the full spectrum never leaves LDS.
+// * Stockham autosort passes, 16 points per thread held in registers: two
+//   radix-16 passes and one radix-M/256 pass (M = 256 .. 4096), so each frame
+//   makes two or three LDS exchanges.  Threads per frame T = M/16; a 256-thread
+//   workgroup holds 256/T frames.  LDS is split into real and imaginary
+//   planes with one padding word per 16 so the strided pass-1 stores are
+//   bank-conflict free.
+// * Twiddles come from a table of W_N^e built on the host in FP64 and rounded
+//   once to FP32 (no fast-math sin/cos on the device).
+// * Frames are independent: a partially filled last workgroup masks its
+//   loads and stores but keeps every barrier.
+#include "internal.h"
+
+namespace cg {
+namespace {
+
+struct c32 {
+  float x, y;
+};
+
+__device__ __forceinline__ c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ c32 cmul(c32 a, c32 b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ c32 mul_mi(c32 a) { return {a.y, -a.x}; }  // -i a
+
+constexpr float kC1 = 0.92387953251128674f;  // cos(pi/8)
+constexpr float kS1 = 0.38268343236508977f;  // sin(pi/8)
+constexpr float kC2 = 0.70710678118654752f;  // cos(pi/4)
+
+// Forward DFTs of length 2, 4, 8, 16 in registers; results in natural order.
+__device__ __forceinline__ void dft2(c32& a, c32& b) {
+  c32 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+__device__ __forceinline__ void dft4(c32& a0, c32& a1, c32& a2, c32& a3) {
+  c32 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+  c32 s13 = cadd(a1, a3), d13 = mul_mi(csub(a1, a3));
+  a0 = cadd(s02, s13);
+  a2 = csub(s02, s13);
+  a1 = cadd(d02, d13);
+  a3 = csub(d02, d13);
+}
+
+__device__ __forceinline__ c32 w8_1(c32 a) { return {kC2 * (a.x + a.y), kC2 * (a.y - a.x)}; }
+__device__ __forceinline__ c32 w8_3(c32 a) { return {kC2 * (a.y - a.x), -kC2 * (a.x + a.y)}; }
+
+__device__ __forceinline__ void dft8(c32* v) {
+  // n = 2 n1 + n2: DFT4 over n1, twiddle W8^(n2 k1), DFT2 over n2.
+  dft4(v[0], v[2], v[4], v[6]);
+  dft4(v[1], v[3], v[5], v[7]);
+  v[3] = w8_1(v[3]);
+  v[5] = mul_mi(v[5]);
+  v[7] = w8_3(v[7]);
+  dft2(v[0], v[1]);
+  dft2(v[2], v[3]);
+  dft2(v[4], v[5]);
+  dft2(v[6], v[7]);
+  // X[k1] in v[2 k1], X[k1 + 4] in v[2 k1 + 1]
+  c32 t[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) t[i] = v[i];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    v[k1] = t[2 * k1];
+    v[k1 + 4] = t[2 * k1 + 1];
+  }
+}
+
+__device__ __forceinline__ void dft16(c32* v) {
+  // n = 4 n1 + n2: DFT4 over n1 for each n2, twiddle W16^(n2 k1), DFT4 over n2.
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+  // v[4 k1 + n2] holds Y[n2][k1]
+  const c32 w1 = {kC1, -kS1}, w3 = {kS1, -kC1}, w9 = {-kC1, kS1};
+  v[5] = cmul(v[5], w1);                       // k1=1 n2=1 : W^1
+  v[6] = {kC2 * (v[6].x + v[6].y), kC2 * (v[6].y - v[6].x)};    // k1=1 n2=2 : W^2
+  v[7] = cmul(v[7], w3);                       // k1=1 n2=3 : W^3
+  v[9] = {kC2 * (v[9].x + v[9].y), kC2 * (v[9].y - v[9].x)};    // k1=2 n2=1 : W^2
+  v[10] = mul_mi(v[10]);                       // k1=2 n2=2 : W^4
+  v[11] = {kC2 * (v[11].y - v[11].x), -kC2 * (v[11].x + v[11].y)};  // k1=2 n2=3 : W^6
+  v[13] = cmul(v[13], w3);                     // k1=3 n2=1 : W^3
+  v[14] = {kC2 * (v[14].y - v[14].x), -kC2 * (v[14].x + v[14].y)};  // k1=3 n2=2 : W^6
+  v[15] = cmul(v[15], w9);                     // k1=3 n2=3 : W^9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  // X[k1 + 4 k2] in v[4 k1 + k2]: transpose the 4x4 block
+  c32 t[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) t[i] = v[i];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[4 * k1 + k2];
+}
+
+template <int R>
+__device__ __forceinline__ void dft_r(c32* v) {
+  if constexpr (R == 2) {
+    dft2(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    dft8(v);
+  } else {
+    dft16(v);
+  }
+}
+
+__device__ __forceinline__ int padx(int i) { return i + (i >> 4); }
+
+template <int LOGM>
+struct FftShape {
+  static constexpr int M = 1 << LOGM;
+  static constexpr int T = M / 16;          // threads per frame
+  static constexpr int FPB = 256 / T;       // frames per 256-thread block
+  static constexpr int PM = M + M / 16;     // padded plane length
+  static constexpr int R3 = M / 256;        // radix of the last pass (1 = none)
+};
+
+template <int LOGM>
+__global__ __launch_bounds__(256) void fft_teeth_kernel(
+    const int32_t* __restrict__ frames, int64_t n_frames, const int32_t* __restrict__ bins,
+    const float* __restrict__ ref, const c32* __restrict__ tw, int k_teeth,
+    float* __restrict__ out_mag, float* __restrict__ out_y) {
+  using S = FftShape<LOGM>;
+  constexpr int M = S::M, T = S::T, FPB = S::FPB, PM = S::PM, R3 = S::R3;
+  constexpr int N = 2 * M;
+  __shared__ float s_re[FPB * PM];
+  __shared__ float s_im[FPB * PM];
+
+  const int tid = threadIdx.x;
+  const int fl = tid / T;
+  const int j = tid - fl * T;
+  const int64_t frame = (int64_t)blockIdx.x * FPB + fl;
+  const bool live = frame < n_frames;
+  float* re = s_re + fl * PM;
+  float* im = s_im + fl * PM;
+
+  c32 v[16];
+  // ---- pass 1: radix 16, Ns = 1, inputs straight from HBM ----
+  {
+    const int32_t* src = frames + frame * M;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      int32_t w = live ? __builtin_nontemporal_load(src + j + r * T) : 0;
+      v[r].x = (float)(int16_t)(w & 0xffff);
+      v[r].y = (float)(w >> 16);
+    }
+    dft16(v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = padx(16 * j + r);
+      re[o] = v[r].x;
+      im[o] = v[r].y;
+    }
+  }
+  __syncthreads();
+  // ---- pass 2: radix 16, Ns = 16 ----
+  {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = padx(j + r * T);
+      v[r].x = re[o];
+      v[r].y = im[o];
+    }
+    __syncthreads();
+    const int jm = j & 15;
+#pragma unroll
+    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw[(jm * r) * (N / 256)]);
+    dft16(v);
+    const int base = (j >> 4) * 256 + jm;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = padx(base + 16 * r);
+      re[o] = v[r].x;
+      im[o] = v[r].y;
+    }
+  }
+  __syncthreads();
+  // ---- pass 3: radix M/256, Ns = 256, 16/R3 butterflies per thread ----
+  if constexpr (R3 > 1) {
+    constexpr int NB = 16 / R3;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int jp = j + T * q;
+#pragma unroll
+      for (int r = 0; r < R3; ++r) {
+        const int o = padx(jp + 256 * r);
+        v[q * R3 + r].x = re[o];
+        v[q * R3 + r].y = im[o];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int jp = j + T * q;
+#pragma unroll
+      for (int r = 1; r < R3; ++r) v[q * R3 + r] = cmul(v[q * R3 + r], tw[2 * jp * r]);
+      dft_r<R3>(v + q * R3);
+#pragma unroll
+      for (int r = 0; r < R3; ++r) {
+        const int o = padx(jp + 256 * r);
+        re[o] = v[q * R3 + r].x;
+        im[o] = v[q * R3 + r].y;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- untangle the real spectrum at the tooth bins, amplitude, / ref ----
+  if (!live) return;
+  for (int i = j; i < k_teeth; i += T) {
+    const int kb = bins[i];
+    const int ia = kb & (M - 1);
+    const int ib = (M - kb) & (M - 1);
+    const c32 a = {re[padx(ia)], im[padx(ia)]};
+    const c32 b = {re[padx(ib)], -im[padx(ib)]};  // conj Z[M-k]
+    const c32 s = cadd(a, b);
+    const c32 o = mul_mi(csub(a, b));
+    const c32 x = cadd(s, cmul(tw[kb], o));
+    const float mag = 0.5f * sqrtf(x.x * x.x + x.y * x.y);
+    const int64_t idx = frame * k_teeth + i;
+    if (out_mag) out_mag[idx] = mag;
+    if (out_y) out_y[idx] = mag / ref[i];
+  }
+}
+
+template <int LOGM>
+hipError_t launch_t(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
+                    float* out_y, hipStream_t s) {
+  using S = FftShape<LOGM>;
+  const int64_t blocks = (nf + S::FPB - 1) / S::FPB;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fft_teeth_kernel<LOGM>, dim3((unsigned)blocks), dim3(256), 0, s,
+                     reinterpret_cast<const int32_t*>(frames), nf, p->d_bins, p->d_ref,
+                     reinterpret_cast<const c32*>(p->d_tw), p->k, out_mag, out_y);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fft_teeth(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
+                            float* out_y, hipStream_t s) {
+  switch (p->m) {
+    case 256: return launch_t<8>(p, frames, nf, out_mag, out_y, s);
+    case 512: return launch_t<9>(p, frames, nf, out_mag, out_y, s);
+    case 1024: return launch_t<10>(p, frames, nf, out_mag, out_y, s);
+    case 2048: return launch_t<11>(p, frames, nf, out_mag, out_y, s);
+    case 4096: return launch_t<12>(p, frames, nf, out_mag, out_y, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+namespace {
+
+__global__ __launch_bounds__(256) void column_mean_kernel(const float* __restrict__ mags,
+                                                          int64_t n, int k,
+                                                          float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  double acc = 0.0;
+  for (int64_t f = 0; f < n; ++f) acc += (double)mags[f * k + i];
+  out[i] = (float)(acc / (double)n);
+}
+
+}  // namespace
+
+hipError_t launch_column_mean(const float* mags, int64_t n, int k, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(column_mean_kernel, dim3((k + 255) / 256), dim3(256), 0, s, mags, n, k, out);
+  return hipGetLastError();
+}
+
+}  // namespace cg

@@ -1,0 +1,59 @@
+// Internal declarations shared by the library's translation units (not part of
+// the public ABI; see include/combgpu.h for that).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/combgpu.h"
+
+struct cg_mlp;  // learned warm-start weights (mlp.hip)
+
+struct cg_plan {
+  int32_t n = 0;          // frame length (samples)
+  int32_t m = 0;          // n / 2 : complex FFT length
+  int32_t k = 0;          // number of teeth
+  double fs = 0.0;        // sample rate (metadata)
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int32_t* d_bins = nullptr;   // [k] tooth bins, optical order
+  float* d_ref = nullptr;      // [k] reference amplitudes
+  float2* d_tw = nullptr;      // [n] W_n^e = (cos 2 pi e/n, -sin 2 pi e/n), e = 0..n-1
+  std::vector<int32_t> h_bins;
+  std::vector<float> h_ref;
+  void* ws = nullptr;          // plan-owned workspace (grown on demand)
+  size_t ws_bytes = 0;
+  cg_mlp* mlp = nullptr;
+};
+
+namespace cg {
+
+constexpr int kWaveSize = 64;
+
+// Record a HIP failure as the thread's error detail and map it to a status.
+cg_status hip_fail(hipError_t e, const char* where);
+void set_detail(const std::string& s);
+
+// A1-A3: int16 frames -> raw tooth amplitudes and/or normalised spectra.
+hipError_t launch_fft_teeth(const cg_plan* p, const int16_t* frames, int64_t n_frames,
+                            float* out_mag, float* out_y, hipStream_t s);
+
+// Column mean over frames of an amplitude image [n][k] -> out[k] (FP64 sums).
+hipError_t launch_column_mean(const float* mags, int64_t n, int k, float* out, hipStream_t s);
+
+// A4: 7x7 median image and start point.
+hipError_t launch_median7(const float* y, int64_t n_frames, int k, float* out_m, hipStream_t s);
+hipError_t launch_init_from_median(const float* m, int64_t n_frames, int k, float* out_p0,
+                                   hipStream_t s);
+
+// A5: Levenberg-Marquardt.  Start point from p0 (if non-null) or computed from
+// the median image m in the kernel prologue.
+hipError_t launch_lm(const float* y, const float* m, const float* p0, int64_t n_frames, int k,
+                     int max_iter, float* params, int32_t* iters, int32_t* status, float* chi2,
+                     hipStream_t s);
+
+}  // namespace cg

@@ -1,0 +1,244 @@
+"""Thin Python binding over the C ABI (argument marshalling only).
+
+Tensors are torch tensors on the GPU; their data pointers and the current
+torch stream are handed to the library, which enqueues its kernels and
+returns.  Outputs the caller does not pass are allocated with torch on the
+input's device.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+DFT_FFT = 0x0
+DFT_MFMA_BF16X3 = 0x1
+DFT_MFMA_FP16 = 0x2
+DFT_MFMA_FP16X2 = 0x3
+FIT_COLD = 0x00
+FIT_WARM_MLP = 0x10
+FIT_NONE = 0x20
+
+FIT_CONVERGED, FIT_MAX_ITER, FIT_SINGULAR, FIT_FALLBACK = 0, 1, 2, 3
+
+
+def _dev_ptr(t, dtype, shape, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """Plan for frames of `frame_len` int16 samples and `len(tooth_bins)` teeth."""
+
+    def __init__(self, frame_len: int, fs: float, tooth_bins, ref_spectrum):
+        self._lib = _lib.load()
+        bins = np.ascontiguousarray(np.asarray(tooth_bins), dtype=np.int32)
+        ref = np.ascontiguousarray(np.asarray(ref_spectrum), dtype=np.float32)
+        if bins.ndim != 1 or ref.shape != bins.shape:
+            raise ValueError("tooth_bins and ref_spectrum must be 1-D of equal length")
+        handle = ctypes.c_void_p()
+        st = self._lib.cg_create_plan(int(frame_len), float(fs),
+                                      bins.ctypes.data_as(_lib._pi32), int(bins.shape[0]),
+                                      ref.ctypes.data_as(_lib._pf32), ctypes.byref(handle))
+        _lib.check(st, "cg_create_plan")
+        self._h = handle
+        self.frame_len = int(frame_len)
+        self.fs = float(fs)
+        self.n_teeth = int(bins.shape[0])
+        self.tooth_bins = bins.copy()
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.cg_destroy_plan(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- plan state -------------------------------------------------------
+    def set_reference(self, ref_spectrum):
+        ref = np.ascontiguousarray(np.asarray(ref_spectrum), dtype=np.float32)
+        if ref.shape != (self.n_teeth,):
+            raise ValueError("reference length must equal n_teeth")
+        _lib.check(self._lib.cg_set_reference(self._h, ref.ctypes.data_as(_lib._pf32)),
+                   "cg_set_reference")
+
+    def info(self):
+        n, k, fs = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _lib.check(self._lib.cg_plan_info(self._h, ctypes.byref(n), ctypes.byref(k),
+                                          ctypes.byref(fs)), "cg_plan_info")
+        return n.value, k.value, fs.value
+
+    def workspace_bytes(self, n_frames: int) -> int:
+        b = ctypes.c_size_t()
+        _lib.check(self._lib.cg_workspace_bytes(self._h, int(n_frames), ctypes.byref(b)),
+                   "cg_workspace_bytes")
+        return b.value
+
+    # -- hot path -----------------------------------------------------------
+    def _frames(self, frames):
+        if frames.dim() != 2 or frames.shape[1] != self.frame_len:
+            raise ValueError(f"frames must be [n, {self.frame_len}]")
+        nf = int(frames.shape[0])
+        return nf, _dev_ptr(frames, torch.int16, (nf, self.frame_len), "frames")
+
+    def process(self, frames, params=None, iters=None, status=None, chi2=None, teeth=None,
+                y=None, flags: int = 0, workspace=None, want=("params",)):
+        """Run the whole path on a batch.  Outputs named in `want` and not
+        passed in are allocated; returns a dict of every output written."""
+        nf, fp = self._frames(frames)
+        dev = frames.device
+        k = self.n_teeth
+        out = {}
+
+        def alloc(name, given, shape, dtype):
+            if given is None and name in want:
+                given = torch.empty(shape, dtype=dtype, device=dev)
+            if given is not None:
+                out[name] = given
+            return given
+
+        fit = flags & 0xF0
+        if fit == FIT_NONE:
+            params = None
+        else:
+            params = alloc("params", params, (nf, 4), torch.float32)
+        iters = alloc("iters", iters, (nf,), torch.int32)
+        status = alloc("status", status, (nf,), torch.int32)
+        chi2 = alloc("chi2", chi2, (nf,), torch.float32)
+        teeth = alloc("teeth", teeth, (nf, k), torch.float32)
+        y = alloc("y", y, (nf, k), torch.float32)
+        ws_ptr, ws_bytes = None, 0
+        if workspace is not None:
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous GPU tensor")
+            ws_ptr = ctypes.c_void_p(workspace.data_ptr())
+            ws_bytes = workspace.numel() * workspace.element_size()
+        st = self._lib.cg_process_batch_ex(
+            self._h, fp, nf,
+            _dev_ptr(params, torch.float32, (nf, 4), "params") if params is not None else None,
+            _dev_ptr(iters, torch.int32, (nf,), "iters"),
+            _dev_ptr(status, torch.int32, (nf,), "status"),
+            _dev_ptr(chi2, torch.float32, (nf,), "chi2"),
+            _dev_ptr(teeth, torch.float32, (nf, k), "teeth"),
+            _dev_ptr(y, torch.float32, (nf, k), "y"),
+            int(flags), ws_ptr, int(ws_bytes), _stream(dev))
+        _lib.check(st, "cg_process_batch_ex")
+        return out
+
+    def process_batch(self, frames, params):
+        """Plain entry point: writes params [n, 4] (centre, width, depth, baseline)."""
+        nf, fp = self._frames(frames)
+        st = self._lib.cg_process_batch(self._h, fp, nf,
+                                        _dev_ptr(params, torch.float32, (nf, 4), "params"),
+                                        _stream(frames.device))
+        _lib.check(st, "cg_process_batch")
+        return params
+
+    def teeth(self, frames, flags: int = DFT_FFT, want_mag=True, want_y=True, out_mag=None,
+              out_y=None):
+        nf, fp = self._frames(frames)
+        dev = frames.device
+        mag, y = out_mag, out_y
+        if mag is None and want_mag:
+            mag = torch.empty((nf, self.n_teeth), dtype=torch.float32, device=dev)
+        if y is None and want_y:
+            y = torch.empty((nf, self.n_teeth), dtype=torch.float32, device=dev)
+        st = self._lib.cg_teeth(self._h, fp, nf,
+                                _dev_ptr(mag, torch.float32, (nf, self.n_teeth), "teeth"),
+                                _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y"),
+                                int(flags), _stream(dev))
+        _lib.check(st, "cg_teeth")
+        return mag, y
+
+    def reference_from_frames(self, ref_frames):
+        nf, fp = self._frames(ref_frames)
+        out = torch.empty((self.n_teeth,), dtype=torch.float32, device=ref_frames.device)
+        st = self._lib.cg_reference_from_frames(self._h, fp, nf,
+                                                ctypes.c_void_p(out.data_ptr()),
+                                                _stream(ref_frames.device))
+        _lib.check(st, "cg_reference_from_frames")
+        return out
+
+    def init_spectra(self, y, want_median=False):
+        nf = int(y.shape[0])
+        yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")
+        p0 = torch.empty((nf, 4), dtype=torch.float32, device=y.device)
+        med = torch.empty((nf, self.n_teeth), dtype=torch.float32, device=y.device) \
+            if want_median else None
+        st = self._lib.cg_init_spectra(self._h, yp, nf, ctypes.c_void_p(p0.data_ptr()),
+                                       _dev_ptr(med, torch.float32, (nf, self.n_teeth), "median"),
+                                       _stream(y.device))
+        _lib.check(st, "cg_init_spectra")
+        return p0, med
+
+    def median_filter(self, y, out=None):
+        nf = int(y.shape[0])
+        yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")
+        if out is None:
+            out = torch.empty((nf, self.n_teeth), dtype=torch.float32, device=y.device)
+        st = self._lib.cg_median_filter(self._h, yp, nf,
+                                        _dev_ptr(out, torch.float32, (nf, self.n_teeth), "median"),
+                                        _stream(y.device))
+        _lib.check(st, "cg_median_filter")
+        return out
+
+    def start_points(self, median, out=None):
+        nf = int(median.shape[0])
+        mp = _dev_ptr(median, torch.float32, (nf, self.n_teeth), "median")
+        if out is None:
+            out = torch.empty((nf, 4), dtype=torch.float32, device=median.device)
+        st = self._lib.cg_start_points(self._h, mp, nf, _dev_ptr(out, torch.float32, (nf, 4), "p0"),
+                                       _stream(median.device))
+        _lib.check(st, "cg_start_points")
+        return out
+
+    def fit_spectra(self, y, p0, max_iter: int = 20, out=None):
+        nf = int(y.shape[0])
+        yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")
+        pp = _dev_ptr(p0, torch.float32, (nf, 4), "p0")
+        dev = y.device
+        if out is None:
+            out = (torch.empty((nf, 4), dtype=torch.float32, device=dev),
+                   torch.empty((nf,), dtype=torch.int32, device=dev),
+                   torch.empty((nf,), dtype=torch.int32, device=dev),
+                   torch.empty((nf,), dtype=torch.float32, device=dev))
+        params, iters, status, chi2 = out
+        _dev_ptr(params, torch.float32, (nf, 4), "params")
+        _dev_ptr(iters, torch.int32, (nf,), "iters")
+        _dev_ptr(status, torch.int32, (nf,), "status")
+        _dev_ptr(chi2, torch.float32, (nf,), "chi2")
+        st = self._lib.cg_fit_spectra(self._h, yp, pp, nf, int(max_iter),
+                                      ctypes.c_void_p(params.data_ptr()),
+                                      ctypes.c_void_p(iters.data_ptr()),
+                                      ctypes.c_void_p(status.data_ptr()),
+                                      ctypes.c_void_p(chi2.data_ptr()), _stream(dev))
+        _lib.check(st, "cg_fit_spectra")
+        return params, iters, status, chi2
