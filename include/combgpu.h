@@ -18,8 +18,9 @@
  *   GPU); "host" pointers are ordinary CPU memory.  The caller owns every
  *   buffer it passes in and keeps device buffers alive until the stream work
  *   has completed.
- * - `stream` is a hipStream_t passed as void*; NULL selects the plan's own
- *   stream.  Work is only enqueued: the call returns before the GPU finishes.
+ * - `stream` is a hipStream_t passed as void*; NULL is HIP's null (default)
+ *   stream.  Work is only enqueued on that stream: the call returns before the
+ *   GPU finishes, and stream order is the only ordering with the caller's work.
  * - Arrays are row-major and contiguous: frames int16 [n_frames][frame_len];
  *   spectra float32 [n_frames][n_teeth]; parameters float32 [n_frames][4] in
  *   the order (centre, width, depth, baseline).
@@ -91,7 +92,8 @@ typedef int32_t cg_status;
  *                 spectrum recorded at the start of the experiment).
  *   out_plan      receives the plan; set to NULL on failure.
  * Arguments are validated on the host before any HIP call.  The plan owns its
- * device tables and a stream; release it with cg_destroy_plan.
+ * device tables (bins, reference, twiddles) and a workspace; release it with
+ * cg_destroy_plan.
  * Errors: CG_ERR_NULL, CG_ERR_UNSUPPORTED, CG_ERR_INVALID_ARG, CG_ERR_BAD_REF,
  * CG_ERR_OOM, CG_ERR_HIP.
  */
@@ -99,10 +101,11 @@ cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins
                          int32_t n_teeth, const float* ref_spectrum, cg_plan** out_plan);
 
 /* Release a plan and everything it owns (NULL is allowed).  Synchronises the
- * plan's stream first. */
+ * device first. */
 cg_status cg_destroy_plan(cg_plan* plan);
 
-/* Replace the plan's reference spectrum (host float32[n_teeth], finite, > 0). */
+/* Replace the plan's reference spectrum (host float32[n_teeth], finite, > 0);
+ * synchronises the device first so no queued work sees a partial update. */
 cg_status cg_set_reference(cg_plan* plan, const float* ref_spectrum);
 
 /* Read back the plan's geometry (any output pointer may be NULL). */
@@ -110,10 +113,9 @@ cg_status cg_plan_info(const cg_plan* plan, int32_t* frame_len, int32_t* n_teeth
 
 /*
  * Bytes of device workspace cg_process_batch_ex needs for `n_frames` frames
- * when the caller supplies one: two float32 [n_frames][n_teeth] images (the
- * normalised spectra and their 7x7 median) and the float32 [n_frames][4]
- * start points, each 256-byte aligned.  The workspace must be 256-byte
- * aligned.
+ * when the caller supplies one: the float32 [n_frames][n_teeth] normalised
+ * spectra and the float32 [n_frames][4] start points, each 256-byte aligned.
+ * The workspace must be 256-byte aligned.
  */
 cg_status cg_workspace_bytes(const cg_plan* plan, int64_t n_frames, size_t* bytes);
 
@@ -177,8 +179,8 @@ cg_status cg_reference_from_frames(cg_plan* plan, const int16_t* ref_frames, int
  * baseline, 0.05, 0.95) (0.05 if baseline <= 0), width = max(2, count of teeth
  * with M < baseline (1 - depth/2)), all decisions in float32.
  *   out_p0      device float32[n_frames][4].
- *   out_median  device float32[n_frames][n_teeth] or NULL.
- * Needs a workspace for M when out_median is NULL (the plan's own is used).
+ *   out_median  device float32[n_frames][n_teeth] or NULL (then M stays on
+ *               chip); must not alias y.
  */
 cg_status cg_init_spectra(cg_plan* plan, const float* y, int64_t n_frames, float* out_p0,
                           float* out_median, void* stream);
@@ -207,6 +209,15 @@ cg_status cg_start_points(cg_plan* plan, const float* median, int64_t n_frames, 
 cg_status cg_fit_spectra(cg_plan* plan, const float* y, const float* p0, int64_t n_frames,
                          int32_t max_iter, float* out_params, int32_t* out_iters,
                          int32_t* out_status, float* out_chi2, void* stream);
+
+/*
+ * Tuning knobs of a plan (launch shapes only; results do not depend on them).
+ *   CG_TUNE_LM_CHUNK  spectra per wavefront in the fit kernel: 0 = chosen from
+ *                     the batch size (default), else a multiple of 4 in 4..256.
+ * Errors: CG_ERR_INVALID_ARG for an unknown knob or value out of range.
+ */
+#define CG_TUNE_LM_CHUNK 1
+cg_status cg_set_tuning(cg_plan* plan, int32_t knob, int32_t value);
 
 /* Static description of a status code. */
 const char* cg_status_string(cg_status status);

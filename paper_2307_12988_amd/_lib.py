@@ -40,6 +40,7 @@ SIGNATURES = {
     "cg_median_filter": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_start_points": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_fit_spectra": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "cg_set_tuning": (_i32, [_vp, _i32, _i32]),
     "cg_status_string": (_c.c_char_p, [_i32]),
     "cg_last_error_detail": (_c.c_char_p, []),
     "cg_version": (_c.c_char_p, []),

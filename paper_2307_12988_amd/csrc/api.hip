@@ -18,9 +18,9 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t image_bytes(int64_t nf, int k) { return align256((size_t)nf * (size_t)k * sizeof(float)); }
 
-// workspace layout: y image | median image | start points [nf][4]
+// workspace layout: y image | start points [nf][4]
 size_t ws_bytes(int64_t nf, int k) {
-  return 2 * image_bytes(nf, k) + align256((size_t)nf * 4 * sizeof(float));
+  return image_bytes(nf, k) + align256((size_t)nf * 4 * sizeof(float));
 }
 
 bool is_pow2(int32_t v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -68,9 +68,7 @@ cg_status check_ref(const float* ref, int32_t k) {
   return CG_OK;
 }
 
-hipStream_t pick(const cg_plan* p, void* s) {
-  return s ? reinterpret_cast<hipStream_t>(s) : p->stream;
-}
+hipStream_t pick(const cg_plan*, void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
 
@@ -90,12 +88,11 @@ cg_status ensure_ws(cg_plan* p, size_t bytes) {
 
 void free_plan(cg_plan* p) {
   if (!p) return;
-  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  (void)hipDeviceSynchronize();
   if (p->d_bins) (void)hipFree(p->d_bins);
   if (p->d_ref) (void)hipFree(p->d_ref);
   if (p->d_tw) (void)hipFree(p->d_tw);
   if (p->ws) (void)hipFree(p->ws);
-  if (p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
 
@@ -169,7 +166,6 @@ cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins
     }                                       \
   } while (0)
   CG_TRY(hipGetDevice(&p->device), "hipGetDevice");
-  CG_TRY(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking), "hipStreamCreate");
   CG_TRY(hipMalloc(&p->d_bins, sizeof(int32_t) * n_teeth), "hipMalloc bins");
   CG_TRY(hipMalloc(&p->d_ref, sizeof(float) * n_teeth), "hipMalloc ref");
   CG_TRY(hipMalloc(&p->d_tw, sizeof(float2) * frame_len), "hipMalloc twiddles");
@@ -193,8 +189,7 @@ cg_status cg_set_reference(cg_plan* p, const float* ref) {
   if (!p) return CG_ERR_NULL;
   cg_status st = cg::check_ref(ref, p->k);
   if (st != CG_OK) return st;
-  hipError_t e = hipStreamSynchronize(p->stream);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  hipError_t e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(p->d_ref, ref, sizeof(float) * p->k, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "cg_set_reference");
   p->h_ref.assign(ref, ref + p->k);
@@ -261,16 +256,14 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
     ws = static_cast<char*>(p->ws);
   }
   float* y = out_y ? out_y : reinterpret_cast<float*>(ws);
-  float* m = reinterpret_cast<float*>(ws + img);
-  float* p0 = reinterpret_cast<float*>(ws + 2 * img);
+  float* p0 = reinterpret_cast<float*>(ws + img);
   hipError_t e = cg::launch_fft_teeth(p, frames, nf, out_teeth, y, s);
   if (e != hipSuccess) return hip_fail(e, "fft_teeth launch");
   if (fit == CG_FIT_NONE) return CG_OK;
-  e = cg::launch_median7(y, nf, p->k, m, s);
-  if (e != hipSuccess) return hip_fail(e, "median7 launch");
-  e = cg::launch_init_from_median(m, nf, p->k, p0, s);
-  if (e != hipSuccess) return hip_fail(e, "init launch");
-  e = cg::launch_lm(y, nullptr, p0, nf, p->k, 20, out_params, out_iters, out_status, out_chi2, s);
+  e = cg::launch_median_start(y, nf, p->k, nullptr, p0, s);
+  if (e != hipSuccess) return hip_fail(e, "median/start launch");
+  e = cg::launch_lm(y, p0, nf, p->k, 20, out_params, out_iters, out_status, out_chi2, s,
+                    p->lm_chunk);
   if (e != hipSuccess) return hip_fail(e, "lm launch");
   return CG_OK;
 }
@@ -313,15 +306,8 @@ cg_status cg_init_spectra(cg_plan* p, const float* y, int64_t nf, float* out_p0,
   if (nf < 0) return CG_ERR_INVALID_ARG;
   if (nf == 0) return CG_OK;
   if (!y) return CG_ERR_NULL;
-  const hipStream_t s = cg::pick(p, stream);
-  float* m = out_median;
-  if (!m) {
-    cg_status st = cg::ensure_ws(p, cg::ws_bytes(nf, p->k));
-    if (st != CG_OK) return st;
-    m = reinterpret_cast<float*>(static_cast<char*>(p->ws) + cg::image_bytes(nf, p->k));
-  }
-  hipError_t e = cg::launch_median7(y, nf, p->k, m, s);
-  if (e == hipSuccess) e = cg::launch_init_from_median(m, nf, p->k, out_p0, s);
+  if (y == out_median) return CG_ERR_INVALID_ARG;
+  hipError_t e = cg::launch_median_start(y, nf, p->k, out_median, out_p0, cg::pick(p, stream));
   if (e != hipSuccess) return hip_fail(e, "init launch");
   return CG_OK;
 }
@@ -333,7 +319,7 @@ cg_status cg_median_filter(cg_plan* p, const float* y, int64_t nf, float* out_me
   if (nf == 0) return CG_OK;
   if (!y) return CG_ERR_NULL;
   if (y == out_median) return CG_ERR_INVALID_ARG;
-  hipError_t e = cg::launch_median7(y, nf, p->k, out_median, cg::pick(p, stream));
+  hipError_t e = cg::launch_median_start(y, nf, p->k, out_median, nullptr, cg::pick(p, stream));
   if (e != hipSuccess) return hip_fail(e, "median launch");
   return CG_OK;
 }
@@ -344,7 +330,7 @@ cg_status cg_start_points(cg_plan* p, const float* median, int64_t nf, float* ou
   if (nf < 0) return CG_ERR_INVALID_ARG;
   if (nf == 0) return CG_OK;
   if (!median) return CG_ERR_NULL;
-  hipError_t e = cg::launch_init_from_median(median, nf, p->k, out_p0, cg::pick(p, stream));
+  hipError_t e = cg::launch_start_points(median, nf, p->k, out_p0, cg::pick(p, stream));
   if (e != hipSuccess) return hip_fail(e, "start point launch");
   return CG_OK;
 }
@@ -357,10 +343,22 @@ cg_status cg_fit_spectra(cg_plan* p, const float* y, const float* p0, int64_t nf
   if (nf == 0) return CG_OK;
   if (!y || !p0) return CG_ERR_NULL;
   const hipStream_t s = cg::pick(p, stream);
-  hipError_t e = cg::launch_lm(y, nullptr, p0, nf, p->k, max_iter, out_params, out_iters,
-                               out_status, out_chi2, s);
+  hipError_t e = cg::launch_lm(y, p0, nf, p->k, max_iter, out_params, out_iters, out_status,
+                               out_chi2, s, p->lm_chunk);
   if (e != hipSuccess) return hip_fail(e, "lm launch");
   return CG_OK;
+}
+
+cg_status cg_set_tuning(cg_plan* p, int32_t knob, int32_t value) {
+  if (!p) return CG_ERR_NULL;
+  switch (knob) {
+    case CG_TUNE_LM_CHUNK:
+      if (value != 0 && (value < 4 || value > 256 || value % 4 != 0)) return CG_ERR_INVALID_ARG;
+      p->lm_chunk = value;
+      return CG_OK;
+    default:
+      return CG_ERR_INVALID_ARG;
+  }
 }
 
 }  // extern "C"

@@ -1,18 +1,26 @@
-"""Generate the branch-free 7x7 median selection network used by the HIP kernels.
+"""Generate the branch-free 7x7 median selection networks used by the HIP kernels.
 
-Build step (run by paper_2307_12988_amd/build.py; output committed as
-median49_net.inc).  The network:
+Build step (run by paper_2307_12988_amd/build.py; output median49_net.inc).
 
-1. sorts each of the 7 columns of the 7x7 window with a 16-comparator
-   7-input sorting network (optional: the kernels may feed pre-sorted columns);
-2. merges the sorted columns with Batcher's odd-even merge (columns padded to
-   8 rows and the window to 8 columns with +inf);
-3. keeps only the min/max operations the middle output (25th smallest of the
-   49 real values) depends on; comparisons against a constant +inf vanish.
+The median of a 7x7 window is the 25th smallest of its 49 values.  The kernel
+sorts each 7-value row segment of the window once (shared by the seven windows
+that contain it) and keeps the last rows in registers while it walks down the
+frames.  Two vertically adjacent windows share six rows, so for each pair:
 
-The result is a list of single min or max operations in SSA form, emitted as
-C++ macros over float registers.  The script also checks the network against
-numpy's median on random inputs with ties before writing the file.
+* CG_MERGE6_R17_24 merges the six shared sorted rows (42 values) and keeps
+  only their ranks 17..24: at most 7 values of the remaining row can fall
+  below or above, so the 17 smallest lie below the median and the 17 largest
+  above it, and the median is the 8th smallest of those 8 values together
+  with the remaining row;
+* CG_MERGE8_7_R7 merges those 8 values with one sorted row and returns the
+  8th smallest, once for each window of the pair.
+
+Both are Batcher odd-even merges (lists padded to 8 with +inf) pruned
+symbolically to the outputs needed; comparisons against a constant +inf
+vanish and only the min or max side of a comparator that is used is emitted.
+CG_SORT7 is the 16-comparator 7-input sorting network.  The script checks the
+composed networks against numpy's median on random inputs with ties before
+writing the file.
 """
 
 import os
@@ -44,15 +52,24 @@ def _oe_merge(w):
     return ops
 
 
-def build(presorted_columns: bool):
-    """Returns (nodes, out_id): nodes is a list of (id, op, a, b) with op in
-    {'min','max'}; ids 0..48 are the inputs v[col*7+row]."""
+def merge_select(list_lens, want_ranks):
+    """Merge sorted lists (inputs numbered consecutively, list by list) with a
+    Batcher merge tree and keep the operations the wanted ranks need.
+    Returns (ops, outputs): ops are (id, 'min'|'max', a, b) in SSA order."""
+    n_in = sum(list_lens)
     nodes = []
-    counter = [49]
-    wires = [INF] * 64
-    for c in range(7):
-        for r in range(7):
-            wires[c * 8 + r] = c * 7 + r
+    counter = [n_in]
+    n_lists = 1
+    while n_lists < len(list_lens):
+        n_lists *= 2
+    per = 8
+    wires = [INF] * (n_lists * per)
+    base = 0
+    for li, ln in enumerate(list_lens):
+        assert ln <= per
+        for r in range(ln):
+            wires[li * per + r] = base + r
+        base += ln
 
     def ce(i, j):
         a, b = wires[i], wires[j]
@@ -67,19 +84,14 @@ def build(presorted_columns: bool):
         nodes.append((hi, "max", a, b))
         wires[i], wires[j] = lo, hi
 
-    if not presorted_columns:
-        for c in range(7):
-            for a, b in SORT7:
-                ce(c * 8 + a, c * 8 + b)
-    size = 8
-    while size < 64:
-        for start in range(0, 64, 2 * size):
+    size = per
+    while size < n_lists * per:
+        for start in range(0, n_lists * per, 2 * size):
             for i, j in _oe_merge(list(range(start, start + 2 * size))):
                 ce(i, j)
         size *= 2
-    out = wires[24]
-    # backward liveness
-    live = {out}
+    outs = [wires[r] for r in want_ranks]
+    live = set(outs)
     kept = []
     for nid, op, a, b in reversed(nodes):
         if nid in live:
@@ -87,45 +99,57 @@ def build(presorted_columns: bool):
             live.add(a)
             live.add(b)
     kept.reverse()
-    return kept, out
+    return kept, outs
 
 
-def evaluate(kept, out, vals):
-    """Run the network on numpy arrays vals [..., 49] (for checking)."""
-    env = {i: vals[..., i] for i in range(49)}
+def evaluate(kept, outs, vals):
+    env = {i: vals[:, i] for i in range(vals.shape[1])}
     for nid, op, a, b in kept:
         env[nid] = np.minimum(env[a], env[b]) if op == "min" else np.maximum(env[a], env[b])
-    return env[out]
+    return np.stack([env[o] for o in outs], axis=1)
 
 
-def emit(kept, out, name):
-    lines = [f"// {name}: {len(kept)} min/max operations", f"#define {name}(V, OUT) do {{ \\"]
+def emit(name, kept, outs, n_in, in_name="IN", out_name="OUT"):
+    lines = [f"// {name}: {len(kept)} min/max operations",
+             f"#define {name}({in_name}, {out_name}) do {{ \\"]
     for nid, op, a, b in kept:
-        sa = f"V[{a}]" if a < 49 else f"t{a}"
-        sb = f"V[{b}]" if b < 49 else f"t{b}"
+        sa = f"{in_name}[{a}]" if a < n_in else f"_t{a}"
+        sb = f"{in_name}[{b}]" if b < n_in else f"_t{b}"
         fn = "fminf" if op == "min" else "fmaxf"
-        lines.append(f"  const float t{nid} = {fn}({sa}, {sb}); \\")
-    lines.append(f"  OUT = t{out}; \\")
+        lines.append(f"  const float _t{nid} = {fn}({sa}, {sb}); \\")
+    for j, o in enumerate(outs):
+        src = f"{in_name}[{o}]" if o < n_in else f"_t{o}"
+        lines.append(f"  {out_name}[{j}] = {src}; \\")
+    lines.append("} while (0)")
+    return "\n".join(lines) + "\n"
+
+
+def emit_sort7(name):
+    lines = [f"// {name}: 16 compare-exchanges, sorts V[0..6] ascending",
+             f"#define {name}(V) do {{ \\"]
+    for a, b in SORT7:
+        lines.append(f"  {{ const float _lo = fminf(V[{a}], V[{b}]); "
+                     f"V[{b}] = fmaxf(V[{a}], V[{b}]); V[{a}] = _lo; }} \\")
     lines.append("} while (0)")
     return "\n".join(lines) + "\n"
 
 
 def main(path):
     _check_sort7()
+    k6, o6 = merge_select([7] * 6, list(range(17, 25)))
+    kf, of = merge_select([8, 7], [7])
     rng = np.random.default_rng(0)
-    text = ["// Generated by gen_median_net.py -- do not edit.",
-            "// Median (25th smallest) of a 7x7 window held as V[col*7+row].", ""]
-    for presorted, name in ((False, "CG_MEDIAN49_RAW"), (True, "CG_MEDIAN49_SORTEDCOLS")):
-        kept, out = build(presorted)
-        for trial in range(4):
-            vals = rng.random((20000, 49)) if trial % 2 == 0 else \
-                rng.integers(0, 5, size=(20000, 49)).astype(np.float64)
-            if presorted:
-                vals = np.sort(vals.reshape(-1, 7, 7), axis=2).reshape(-1, 49)
-            got = evaluate(kept, out, vals)
-            want = np.sort(vals, axis=1)[:, 24]
-            assert np.array_equal(got, want), name
-        text.append(emit(kept, out, name))
+    for trial in range(4):
+        v = rng.random((20000, 49)) if trial % 2 == 0 else \
+            rng.integers(0, 5, size=(20000, 49)).astype(np.float64)
+        v = np.sort(v.reshape(-1, 7, 7), axis=2).reshape(-1, 49)
+        a = evaluate(k6, o6, v[:, :42])
+        got = evaluate(kf, of, np.concatenate([a, v[:, 42:]], axis=1))[:, 0]
+        assert np.array_equal(got, np.sort(v, axis=1)[:, 24])
+    text = ["// Generated by gen_median_net.py -- do not edit.", ""]
+    text.append(emit_sort7("CG_SORT7"))
+    text.append(emit("CG_MERGE6_R17_24", k6, o6, 42))
+    text.append(emit("CG_MERGE8_7_R7", kf, of, 15))
     with open(path, "w") as fh:
         fh.write("\n".join(text))
     return 0

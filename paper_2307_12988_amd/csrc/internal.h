@@ -19,7 +19,6 @@ struct cg_plan {
   int32_t k = 0;          // number of teeth
   double fs = 0.0;        // sample rate (metadata)
   int device = 0;
-  hipStream_t stream = nullptr;
   int32_t* d_bins = nullptr;   // [k] tooth bins, optical order
   float* d_ref = nullptr;      // [k] reference amplitudes
   float2* d_tw = nullptr;      // [n] W_n^e = (cos 2 pi e/n, -sin 2 pi e/n), e = 0..n-1
@@ -28,6 +27,7 @@ struct cg_plan {
   void* ws = nullptr;          // plan-owned workspace (grown on demand)
   size_t ws_bytes = 0;
   cg_mlp* mlp = nullptr;
+  int32_t lm_chunk = 0;        // spectra per wave in the fit kernel (0 = auto)
 };
 
 namespace cg {
@@ -45,15 +45,19 @@ hipError_t launch_fft_teeth(const cg_plan* p, const int16_t* frames, int64_t n_f
 // Column mean over frames of an amplitude image [n][k] -> out[k] (FP64 sums).
 hipError_t launch_column_mean(const float* mags, int64_t n, int k, float* out, hipStream_t s);
 
-// A4: 7x7 median image and start point.
-hipError_t launch_median7(const float* y, int64_t n_frames, int k, float* out_m, hipStream_t s);
-hipError_t launch_init_from_median(const float* m, int64_t n_frames, int k, float* out_p0,
-                                   hipStream_t s);
+// A4: 7x7 median image (out_m, may be null) and/or start points (out_p0, may
+// be null) from normalised spectra, in one kernel.
+hipError_t launch_median_start(const float* y, int64_t n_frames, int k, float* out_m,
+                               float* out_p0, hipStream_t s);
+// Start points from a given median image.
+hipError_t launch_start_points(const float* m, int64_t n_frames, int k, float* out_p0,
+                               hipStream_t s);
 
-// A5: Levenberg-Marquardt.  Start point from p0 (if non-null) or computed from
-// the median image m in the kernel prologue.
-hipError_t launch_lm(const float* y, const float* m, const float* p0, int64_t n_frames, int k,
-                     int max_iter, float* params, int32_t* iters, int32_t* status, float* chi2,
-                     hipStream_t s);
+// A5: Levenberg-Marquardt from start points p0.  chunk = spectra per wave
+// (<= 0: chosen from n_frames).
+int lm_chunk(int64_t n_frames);
+hipError_t launch_lm(const float* y, const float* p0, int64_t n_frames, int k, int max_iter,
+                     float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
+                     int chunk = 0);
 
 }  // namespace cg

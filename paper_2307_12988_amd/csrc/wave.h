@@ -1,4 +1,4 @@
-// Wave-level (64-lane) helpers shared by the initializer and fit kernels.
+// Wave-level (64-lane) and 16-lane-group helpers shared by the kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,16 +9,66 @@ namespace cg {
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
-// Butterfly all-reduce: every lane ends with the same, bit-identical sum
-// (each step adds the same two operands in every lane of a pair).
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
+// ---------------------------------------------------------------------------
+// DPP permutations inside a row of 16 lanes (gfx9 DPP control codes).
+//   0xB1 quad_perm [1,0,3,2]  (lane ^ 1)
+//   0x4E quad_perm [2,3,0,1]  (lane ^ 2)
+//   0x141 row_half_mirror     (lane -> 7 - lane within each 8)
+//   0x140 row_mirror          (lane -> 15 - lane within each 16)
+// After the quad steps every lane of a quad holds the same value, so the two
+// mirror steps pair each quad (then each half row) with its partner; each step
+// adds the same two operands in both lanes of a pair, so all 16 lanes end with
+// bit-identical sums.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = dpp_i<CTRL>(__double2loint(v));
+  const int hi = dpp_i<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ int wave_count(bool pred) {
-  return __popcll(__ballot(pred));
+__device__ __forceinline__ float sum16(float v) {
+  v += dpp_f<0xB1>(v);
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  v += dpp_f<0x140>(v);
+  return v;
+}
+__device__ __forceinline__ double sum16(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return v;
+}
+__device__ __forceinline__ int sum16(int v) {
+  v += dpp_i<0xB1>(v);
+  v += dpp_i<0x4E>(v);
+  v += dpp_i<0x141>(v);
+  v += dpp_i<0x140>(v);
+  return v;
+}
+__device__ __forceinline__ uint64_t min16(uint64_t v) {
+#define CG_MIN_STEP(C)                                                                 \
+  {                                                                                    \
+    const uint32_t lo = (uint32_t)dpp_i<C>((int)(uint32_t)v);                           \
+    const uint32_t hi = (uint32_t)dpp_i<C>((int)(uint32_t)(v >> 32));                   \
+    const uint64_t o = ((uint64_t)hi << 32) | lo;                                      \
+    v = o < v ? o : v;                                                                 \
+  }
+  CG_MIN_STEP(0xB1)
+  CG_MIN_STEP(0x4E)
+  CG_MIN_STEP(0x141)
+  CG_MIN_STEP(0x140)
+#undef CG_MIN_STEP
+  return v;
 }
 
 // Order-preserving map of float bits to unsigned (negatives below positives).
@@ -30,39 +80,33 @@ __device__ __forceinline__ float key_float(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
-// Start point of the Lorentzian fit from one row of the 7x7-median image.
-// Lane l holds row values i = l + 64 q, q < Q (masked beyond k).
-//   c0 = first index of the minimum, b0 = lower median (order statistic
-//   (k-1)/2), d0 = clip(1 - M[c0]/b0, 0.05, 0.95) (0.05 if b0 <= 0),
-//   w0 = max(2, #{M < b0 (1 - d0/2)}); decisions in float32, IEEE rounding.
+// ---------------------------------------------------------------------------
+// Start point of the Lorentzian fit from one row of the 7x7-median image,
+// computed by a group of 16 lanes.  Lane gl of the group holds row values
+// i = gl + 16 q (q < Q), masked beyond k.
+//   c0 = first index of the minimum; b0 = lower median (order statistic
+//   (k-1)/2, by a 32-step radix select on order-preserving keys);
+//   d0 = clip(1 - M[c0]/b0, 0.05, 0.95), 0.05 if b0 <= 0;
+//   w0 = max(2, #{M < b0 (1 - d0/2)}).
+// The arithmetic that decides d0 and the count uses IEEE float32 operations in
+// that order (no contraction), so identical inputs give identical results.
 template <int Q>
-__device__ __forceinline__ void start_point(const float (&mv)[Q], int k, float& c0, float& w0,
-                                            float& d0, float& b0) {
-  const int lane = lane_id();
-  // argmin with ties to the lowest index
-  float best = __builtin_inff();
-  int besti = 0x7fffffff;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int i = lane + 64 * q;
-    if (i < k && (mv[q] < best || (mv[q] == best && i < besti))) {
-      best = mv[q];
-      besti = i;
-    }
-  }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const float ob = __shfl_xor(best, m, 64);
-    const int oi = __shfl_xor(besti, m, 64);
-    if (ob < best || (ob == best && oi < besti)) {
-      best = ob;
-      besti = oi;
-    }
-  }
-  // radix select of the lower median on order-preserving keys
+__device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float& c0, float& w0,
+                                              float& d0, float& b0) {
+  const int gl = lane_id() & 15;
+  uint64_t best = ~0ull;
   uint32_t keys[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) keys[q] = float_key(mv[q]);
+  for (int q = 0; q < Q; ++q) {
+    const int i = gl + 16 * q;
+    keys[q] = float_key(mv[q]);
+    const uint64_t cand = ((uint64_t)keys[q] << 32) | (uint32_t)i;
+    if (i < k && cand < best) best = cand;
+  }
+  best = min16(best);
+  const int besti = (int)(uint32_t)best;
+  const float bestv = key_float((uint32_t)(best >> 32));
+
   int rank = (k - 1) / 2;
   uint32_t prefix = 0u, himask = 0u;
   for (int bit = 31; bit >= 0; --bit) {
@@ -70,10 +114,10 @@ __device__ __forceinline__ void start_point(const float (&mv)[Q], int k, float& 
     int c = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int i = lane + 64 * q;
-      const bool match = (i < k) && (((keys[q] ^ prefix) & himask) == 0u) && !(keys[q] & b);
-      c += wave_count(match);
+      const int i = gl + 16 * q;
+      c += (i < k) && (((keys[q] ^ prefix) & himask) == 0u) && !(keys[q] & b);
     }
+    c = sum16(c);
     if (rank >= c) {
       prefix |= b;
       rank -= c;
@@ -83,7 +127,7 @@ __device__ __forceinline__ void start_point(const float (&mv)[Q], int k, float& 
   const float med = key_float(prefix);
   float d;
   if (med > 0.0f) {
-    d = __fsub_rn(1.0f, __fdiv_rn(best, med));
+    d = __fsub_rn(1.0f, __fdiv_rn(bestv, med));
     d = fminf(fmaxf(d, 0.05f), 0.95f);
   } else {
     d = 0.05f;
@@ -92,13 +136,43 @@ __device__ __forceinline__ void start_point(const float (&mv)[Q], int k, float& 
   int cnt = 0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int i = lane + 64 * q;
-    cnt += wave_count(i < k && mv[q] < thr);
+    const int i = gl + 16 * q;
+    cnt += (i < k) && (mv[q] < thr);
   }
+  cnt = sum16(cnt);
   c0 = (float)besti;
   w0 = (float)(cnt > 2 ? cnt : 2);
   d0 = d;
   b0 = med;
 }
+
+// Dispatch a runtime tooth count to the smallest per-lane slot count that
+// covers it with 16 lanes: Q in {1, 2, 4, 8, 14, 20, 28} (k <= 16 .. 448).
+#define CG_DISPATCH_Q16(k, CALL)        \
+  do {                                   \
+    const int _k = (k);                  \
+    if (_k <= 16) {                      \
+      constexpr int Q = 1;               \
+      CALL;                              \
+    } else if (_k <= 32) {               \
+      constexpr int Q = 2;               \
+      CALL;                              \
+    } else if (_k <= 64) {               \
+      constexpr int Q = 4;               \
+      CALL;                              \
+    } else if (_k <= 128) {              \
+      constexpr int Q = 8;               \
+      CALL;                              \
+    } else if (_k <= 224) {              \
+      constexpr int Q = 14;              \
+      CALL;                              \
+    } else if (_k <= 320) {              \
+      constexpr int Q = 20;              \
+      CALL;                              \
+    } else {                             \
+      constexpr int Q = 28;              \
+      CALL;                              \
+    }                                    \
+  } while (0)
 
 }  // namespace cg

@@ -24,6 +24,7 @@ FIT_WARM_MLP = 0x10
 FIT_NONE = 0x20
 
 FIT_CONVERGED, FIT_MAX_ITER, FIT_SINGULAR, FIT_FALLBACK = 0, 1, 2, 3
+TUNE_LM_CHUNK = 1
 
 
 def _dev_ptr(t, dtype, shape, name):
@@ -95,6 +96,9 @@ class Plan:
         _lib.check(self._lib.cg_plan_info(self._h, ctypes.byref(n), ctypes.byref(k),
                                           ctypes.byref(fs)), "cg_plan_info")
         return n.value, k.value, fs.value
+
+    def set_tuning(self, knob: int, value: int):
+        _lib.check(self._lib.cg_set_tuning(self._h, int(knob), int(value)), "cg_set_tuning")
 
     def workspace_bytes(self, n_frames: int) -> int:
         b = ctypes.c_size_t()
@@ -187,10 +191,12 @@ class Plan:
         _lib.check(st, "cg_reference_from_frames")
         return out
 
-    def init_spectra(self, y, want_median=False):
+    def init_spectra(self, y, want_median=False, out_p0=None):
         nf = int(y.shape[0])
         yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")
-        p0 = torch.empty((nf, 4), dtype=torch.float32, device=y.device)
+        p0 = out_p0 if out_p0 is not None else \
+            torch.empty((nf, 4), dtype=torch.float32, device=y.device)
+        _dev_ptr(p0, torch.float32, (nf, 4), "p0")
         med = torch.empty((nf, self.n_teeth), dtype=torch.float32, device=y.device) \
             if want_median else None
         st = self._lib.cg_init_spectra(self._h, yp, nf, ctypes.c_void_p(p0.data_ptr()),

@@ -94,6 +94,9 @@ def test_null_arguments(lib):
     assert lib.cg_reference_from_frames(None, None, 1, None, None) == CODES["CG_ERR_NULL"]
     assert lib.cg_set_reference(None, None) == CODES["CG_ERR_NULL"]
     assert lib.cg_plan_info(None, None, None, None) == CODES["CG_ERR_NULL"]
+    assert lib.cg_set_tuning(None, 1, 0) == CODES["CG_ERR_NULL"]
+    assert lib.cg_median_filter(None, None, 0, None, None) == CODES["CG_ERR_NULL"]
+    assert lib.cg_start_points(None, None, 0, None, None) == CODES["CG_ERR_NULL"]
     sz = ctypes.c_size_t()
     assert lib.cg_workspace_bytes(None, 10, ctypes.byref(sz)) == CODES["CG_ERR_NULL"]
 
