@@ -107,6 +107,97 @@ def cpu_baseline(spec, frames, gpu_params, ref_frames, n_sample):
     }
 
 
+def form_errors(spec, frames, ref_frames, mags_by_form, n_sample):
+    """CPU-baseline leg of the precision workload: FP64 oracle amplitudes of the
+    first frames, and each form's relative error against them."""
+    import oracle
+    t0 = time.perf_counter()
+    m_or = oracle.tooth_magnitudes(frames[:n_sample], spec.bins)
+    dt = time.perf_counter() - t0
+    out = {}
+    for name, mags in mags_by_form.items():
+        err = np.abs(mags[:n_sample].astype(np.float64) - m_or) / m_or
+        out[name] = {"max_rel_err": float(err.max()), "rms_rel_err": float(np.sqrt(np.mean(err ** 2)))}
+    return out, n_sample / dt
+
+
+def precision_forms(args, torch, cg, dev):
+    spec = synth.spec_precision()
+    nf = 131072 if args.frames == 65536 else args.frames
+    n, k = spec.n, spec.k
+    pool_n = max(1, min(args.pool, 2))
+    _log(f"generating {pool_n} batches of {nf} x {n} int16 ...")
+    pool_np, ref_np = make_pool(spec, nf, pool_n, workers=pool_n)
+    pool = [torch.from_numpy(fr).to(dev) for fr in pool_np]
+    plan = cg.Plan(n, spec.fs, spec.bins, np.ones(k, dtype=np.float32))
+    plan.set_reference(plan.reference_from_frames(torch.from_numpy(ref_np).to(dev)).cpu().numpy())
+    ws = torch.empty(plan.workspace_bytes(nf), dtype=torch.uint8, device=dev)
+    params = torch.empty((nf, 4), dtype=torch.float32, device=dev)
+    status = torch.empty((nf,), dtype=torch.int32, device=dev)
+    mag = torch.empty((nf, k), dtype=torch.float32, device=dev)
+    forms = {"fft_fp32": cg.DFT_FFT, "mfma_bf16x3": cg.DFT_MFMA_BF16X3,
+             "mfma_fp16": cg.DFT_MFMA_FP16, "mfma_fp16x2": cg.DFT_MFMA_FP16X2}
+    stream = torch.cuda.current_stream(dev)
+    lines, sample_mags = [], {}
+    for name, flag in forms.items():
+        for i in range(args.warmup):
+            plan.process(pool[i % pool_n], params=params, status=status, workspace=ws,
+                         flags=flag, want=())
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            plan.process(pool[i % pool_n], params=params, status=status, workspace=ws,
+                         flags=flag, want=())
+        torch.cuda.synchronize(dev)
+        wall = time.perf_counter() - t0
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        reps = 3
+        ev[0].record(stream)
+        for r in range(reps):
+            plan.teeth(pool[r % pool_n], flags=flag, want_mag=True, want_y=False, out_mag=mag)
+        ev[1].record(stream)
+        torch.cuda.synchronize(dev)
+        t_ms = ev[0].elapsed_time(ev[1]) / reps
+        sample_mags[name] = mag[:4096].cpu().numpy()
+        flop_pass = 2.0 * nf * n * 2 * k
+        passes = {"fft_fp32": 0, "mfma_bf16x3": 3, "mfma_fp16": 1, "mfma_fp16x2": 2}[name]
+        line = {"metric": METRIC, "value": nf * n * 2 * args.steps / wall / 1e9, "unit": "GB/s",
+                "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None,
+                "dtype": {"fft_fp32": "f32", "mfma_bf16x3": "bf16", "mfma_fp16": "f16",
+                          "mfma_fp16x2": "f16"}[name],
+                "data": "synthetic",
+                "config": {"workload": f"precision form {name}: {nf} frames x {n} int16 samples, "
+                                       f"{k} teeth, cold-start fit", "form": name},
+                "spectra_per_s": nf * args.steps / wall,
+                "converged_frac": float((status == 0).float().mean().item()),
+                "tooth_transform_ms": t_ms}
+        if passes:
+            tf = flop_pass * passes / (t_ms * 1e-3) / 1e12
+            line["roofline"] = {"kernel": "mfma_teeth", "bound": "mfma", "achieved": tf,
+                                "peak": 2500.0, "unit": "TFLOP/s", "frac": tf / 2500.0,
+                                "traffic": None}
+        else:
+            gbs = nf * (2 * n + 4 * k) / (t_ms * 1e-3) / 1e9
+            line["roofline"] = {"kernel": "fft_teeth", "bound": "hbm", "achieved": gbs,
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                                "traffic": None}
+        lines.append(line)
+    if not args.no_cpu_baseline:
+        errs, sps = form_errors(spec, pool_np[0], ref_np, sample_mags, 4096)
+        fft_t = lines[0]["tooth_transform_ms"]
+        for line in lines:
+            line["cpu_baseline"] = {"value": sps * n * 2 / 1e9, "unit": "GB/s", "cores": None,
+                                    "kind": "oracle",
+                                    "sample": "FP64 DFT amplitudes of the first 4096 frames"}
+            line["amplitude_error_vs_oracle"] = errs[line["config"]["form"]]
+            line["speedup_vs_fft_path_transform"] = fft_t / line["tooth_transform_ms"]
+    for line in lines:
+        print(json.dumps(line), flush=True)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,8 +205,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--pool", type=int, default=4, help="distinct batches resident in HBM")
     ap.add_argument("--frames", type=int, default=65536)
-    ap.add_argument("--cpu-frames", type=int, default=12288)
+    ap.add_argument("--cpu-frames", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["paper_rate", "precision"], default="paper_rate",
+                    help="paper_rate: the headline line; precision: 131072 x 4096 frames, one "
+                         "line per tooth-DFT form (FFT and the three matrix-core forms)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (reference for "
+                         "the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -129,6 +226,16 @@ def main():
     import paper_2307_12988_amd as cg
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        print(json.dumps({"calibrate_copy_bytes": 1 << 30, "copies": 5}), flush=True)
+        return
+    if args.workload == "precision":
+        return precision_forms(args, torch, cg, dev)
     spec = synth.spec_paper_rate()
     nf, n, k = args.frames, spec.n, spec.k
     _log(f"generating {args.pool} batches of {nf} x {n} int16 ...")

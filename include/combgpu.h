@@ -144,6 +144,10 @@ cg_status cg_process_batch(cg_plan* plan, const int16_t* frames, int64_t n_frame
  *   workspace   device buffer of >= cg_workspace_bytes() bytes, or NULL to use
  *               the plan's own (then workspace_bytes is ignored).
  * out_params may be NULL only with CG_FIT_NONE.
+ * The CG_DFT_MFMA_* forms evaluate the DFT at the tooth bins directly as the
+ * product frames [n][frame_len] x basis [frame_len][2 n_teeth] on the matrix
+ * cores (FP32 accumulation) instead of the FFT; they need 16-byte aligned
+ * frames, and the first call with a form builds its basis (device allocation).
  * Errors: CG_ERR_WORKSPACE if workspace_bytes is too small; CG_ERR_STATE for
  * CG_FIT_WARM_MLP before cg_set_mlp; CG_ERR_INVALID_ARG for unknown flags.
  */

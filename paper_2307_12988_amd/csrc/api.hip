@@ -93,6 +93,10 @@ void free_plan(cg_plan* p) {
   if (p->d_ref) (void)hipFree(p->d_ref);
   if (p->d_tw) (void)hipFree(p->d_tw);
   if (p->ws) (void)hipFree(p->ws);
+  for (auto* b : p->d_mfma_bf)
+    if (b) (void)hipFree(b);
+  for (auto* b : p->d_mfma_h)
+    if (b) (void)hipFree(b);
   delete p;
 }
 
@@ -232,8 +236,12 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
     return CG_ERR_INVALID_ARG;
   }
   if (dft != CG_DFT_FFT) {
-    cg::set_detail("MFMA tooth-DFT forms are not built in this library version");
-    return CG_ERR_UNSUPPORTED;
+    if (!cg::aligned(frames, 16)) {
+      cg::set_detail("matrix-core DFT forms need 16-byte aligned frames");
+      return CG_ERR_INVALID_ARG;
+    }
+    cg_status st = cg::mfma_prepare(p, dft);
+    if (st != CG_OK) return st;
   }
   if (fit == CG_FIT_WARM_MLP) {
     cg::set_detail("learned warm start not available");
@@ -257,8 +265,9 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
   }
   float* y = out_y ? out_y : reinterpret_cast<float*>(ws);
   float* p0 = reinterpret_cast<float*>(ws + img);
-  hipError_t e = cg::launch_fft_teeth(p, frames, nf, out_teeth, y, s);
-  if (e != hipSuccess) return hip_fail(e, "fft_teeth launch");
+  hipError_t e = dft == CG_DFT_FFT ? cg::launch_fft_teeth(p, frames, nf, out_teeth, y, s)
+                                   : cg::launch_mfma_teeth(p, dft, frames, nf, out_teeth, y, s);
+  if (e != hipSuccess) return hip_fail(e, "tooth transform launch");
   if (fit == CG_FIT_NONE) return CG_OK;
   e = cg::launch_median_start(y, nf, p->k, nullptr, p0, s);
   if (e != hipSuccess) return hip_fail(e, "median/start launch");

@@ -28,6 +28,10 @@ struct cg_plan {
   size_t ws_bytes = 0;
   cg_mlp* mlp = nullptr;
   int32_t lm_chunk = 0;        // spectra per wave in the fit kernel (0 = auto)
+  // tooth-DFT bases for the matrix-core forms, [ceil(k/64)*64][n], built on
+  // first use: bf16 cos_hi, cos_lo, sin_hi, sin_lo / fp16 cos, sin
+  uint16_t* d_mfma_bf[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint16_t* d_mfma_h[2] = {nullptr, nullptr};
 };
 
 namespace cg {
@@ -41,6 +45,12 @@ void set_detail(const std::string& s);
 // A1-A3: int16 frames -> raw tooth amplitudes and/or normalised spectra.
 hipError_t launch_fft_teeth(const cg_plan* p, const int16_t* frames, int64_t n_frames,
                             float* out_mag, float* out_y, hipStream_t s);
+
+// A6: tooth DFT on the matrix cores (form = CG_DFT_MFMA_*); mfma_prepare
+// builds the plan's basis for the form on first use.
+cg_status mfma_prepare(cg_plan* p, uint32_t form);
+hipError_t launch_mfma_teeth(const cg_plan* p, uint32_t form, const int16_t* frames,
+                             int64_t n_frames, float* out_mag, float* out_y, hipStream_t s);
 
 // Column mean over frames of an amplitude image [n][k] -> out[k] (FP64 sums).
 hipError_t launch_column_mean(const float* mags, int64_t n, int k, float* out, hipStream_t s);
