@@ -5,9 +5,11 @@
 // cos(2 pi k_i t / N) and -sin(2 pi k_i t / N).  On gfx950 it runs on
 // v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation, in three forms:
 //
-//   BF16X3  x = x_hi + x_lo exactly (x_hi = x with its low byte cleared, both
-//           parts exact in bf16), W = W_hi + W_lo (bf16 rounding of W and of
-//           the FP64 remainder); sum x_hi W_hi + x_hi W_lo + x_lo W_hi.
+//   BF16X3  x = x_hi + x_lo exactly: x_hi keeps the 8 leading significant bits
+//           of x (bf16 truncation), x_lo = x - x_hi has at most 8 significant
+//           bits and |x_lo| < 2^-7 |x|; W = W_hi + W_lo (bf16 rounding of W and
+//           of the FP64 remainder).  Sum x_hi W_hi + x_hi W_lo + x_lo W_hi; the
+//           dropped x_lo W_lo is below 2^-16 |x W|.
 //   FP16    x and W rounded to fp16; one product.
 //   FP16X2  x = x_hi + x_lo exactly (low 5 bits split off, both exact in
 //           fp16), W rounded to fp16; two products.
@@ -16,8 +18,8 @@
 // same outputs as the FFT path.  The basis is built on the host in FP64 from
 // the integer phase index (k t mod N) and rounded once.
 //
-// Tiling: a 256-thread block computes 64 frames x 64 teeth (cos and sin
-// accumulators for each); the four waves take 32 x 32 quadrants, i.e. 2 x 2
+// Tiling: a 256-thread block computes 128 frames x 64 teeth (cos and sin
+// accumulators for each); each wave takes 32 frames x 64 teeth, i.e. 2 x 4
 // MFMA tiles of 16 x 16, for both the cos and the sin columns.  Each step of 32
 // samples stages the frames (converted to the operand format) and the basis
 // slices in LDS; the next step's global loads are issued before the current
@@ -37,7 +39,7 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 64;       // frames per block
+constexpr int BM = 128;      // frames per block
 constexpr int BT = 64;       // teeth per block
 constexpr int KS = 32;       // samples per step
 constexpr int PITCH = 40;    // LDS row pitch in 16-bit elements (80 B, 16-B aligned)
@@ -68,32 +70,36 @@ __global__ __launch_bounds__(256) void mfma_teeth_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave & 1, wc = wave >> 1;
+  const int wr = wave;
   const int tb = blockIdx.x % tooth_blocks;
   const int64_t f0 = (int64_t)(blockIdx.x / tooth_blocks) * BM;
   const int t0 = tb * BT;
   const int kpad = tooth_blocks * BT;
 
-  // staging assignment: each thread moves 8 consecutive samples of one row
+  // staging assignment: each thread moves 8 consecutive samples of two frame
+  // rows (srow, srow + 64) and of one basis row (srow)
   const int srow = tid >> 2;
   const int scol = (tid & 3) * 8;
-  const int64_t frow = f0 + srow;
-  const bool frow_ok = frow < nf;
-  const int16_t* a_src = frames + (frow_ok ? frow : 0) * (int64_t)n + scol;
+  const int64_t frow0 = f0 + srow, frow1 = f0 + 64 + srow;
+  const bool ok0 = frow0 < nf, ok1 = frow1 < nf;
+  const int16_t* a_src0 = frames + (ok0 ? frow0 : 0) * (int64_t)n + scol;
+  const int16_t* a_src1 = frames + (ok1 ? frow1 : 0) * (int64_t)n + scol;
   const size_t b_off = (size_t)(t0 + srow) * n + scol;
 
-  f32x4 acc_c[2][2], acc_s[2][2];
+  f32x4 acc_c[2][4], acc_s[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < 4; ++j) {
       acc_c[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
       acc_s[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
 
-  u16x8 ra, rbch, rbsh, rbcl, rbsl;
+  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+  u16x8 ra0, ra1, rbch, rbsh, rbcl, rbsl;
   auto gload = [&](int s0) {
-    ra = frow_ok ? *reinterpret_cast<const u16x8*>(a_src + s0) : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    ra0 = ok0 ? *reinterpret_cast<const u16x8*>(a_src0 + s0) : zero8;
+    ra1 = ok1 ? *reinterpret_cast<const u16x8*>(a_src1 + s0) : zero8;
     rbch = *reinterpret_cast<const u16x8*>(bc_hi + b_off + s0);
     rbsh = *reinterpret_cast<const u16x8*>(bs_hi + b_off + s0);
     if constexpr (SPLIT_B) {
@@ -101,15 +107,15 @@ __global__ __launch_bounds__(256) void mfma_teeth_kernel(
       rbsl = *reinterpret_cast<const u16x8*>(bs_lo + b_off + s0);
     }
   };
-  auto lstore = [&]() {
-    u16x8 hi, lo;
+  auto convert = [&](const u16x8& ra, u16x8& hi, u16x8& lo) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int x = (int)(int16_t)ra[j];
       if constexpr (FORM == 0) {
-        const int xh = x & ~0xff;
-        hi[j] = bf16_bits_exact((float)xh);
-        lo[j] = bf16_bits_exact((float)(x - xh));
+        const float xf = (float)x;
+        const float xh = __uint_as_float(__float_as_uint(xf) & 0xffff0000u);
+        hi[j] = bf16_bits_exact(xh);
+        lo[j] = bf16_bits_exact(xf - xh);
       } else if constexpr (FORM == 1) {
         hi[j] = f16_bits((float)x);
       } else {
@@ -118,8 +124,15 @@ __global__ __launch_bounds__(256) void mfma_teeth_kernel(
         lo[j] = f16_bits((float)(x - xh));
       }
     }
+  };
+  auto lstore = [&]() {
+    u16x8 hi, lo;
+    convert(ra0, hi, lo);
     *reinterpret_cast<u16x8*>(sa_hi + srow * PITCH + scol) = hi;
     if constexpr (SPLIT_A) *reinterpret_cast<u16x8*>(sa_lo + srow * PITCH + scol) = lo;
+    convert(ra1, hi, lo);
+    *reinterpret_cast<u16x8*>(sa_hi + (64 + srow) * PITCH + scol) = hi;
+    if constexpr (SPLIT_A) *reinterpret_cast<u16x8*>(sa_lo + (64 + srow) * PITCH + scol) = lo;
     *reinterpret_cast<u16x8*>(sc_hi + srow * PITCH + scol) = rbch;
     *reinterpret_cast<u16x8*>(ss_hi + srow * PITCH + scol) = rbsh;
     if constexpr (SPLIT_B) {
@@ -136,24 +149,27 @@ __global__ __launch_bounds__(256) void mfma_teeth_kernel(
     lstore();
     __syncthreads();
     if (s0 + KS < n) gload(s0 + KS);
-    u16x8 ah[2], al[2], ch[2], sh[2], cl[2], sl[2];
+    u16x8 ah[2], al[2], ch[4], sh[4], cl[4], sl[4];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int row = wr * 32 + i * 16 + fr;
       ah[i] = *reinterpret_cast<const u16x8*>(sa_hi + row * PITCH + kq);
       if constexpr (SPLIT_A) al[i] = *reinterpret_cast<const u16x8*>(sa_lo + row * PITCH + kq);
-      const int col = wc * 32 + i * 16 + fr;
-      ch[i] = *reinterpret_cast<const u16x8*>(sc_hi + col * PITCH + kq);
-      sh[i] = *reinterpret_cast<const u16x8*>(ss_hi + col * PITCH + kq);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = j * 16 + fr;
+      ch[j] = *reinterpret_cast<const u16x8*>(sc_hi + col * PITCH + kq);
+      sh[j] = *reinterpret_cast<const u16x8*>(ss_hi + col * PITCH + kq);
       if constexpr (SPLIT_B) {
-        cl[i] = *reinterpret_cast<const u16x8*>(sc_lo + col * PITCH + kq);
-        sl[i] = *reinterpret_cast<const u16x8*>(ss_lo + col * PITCH + kq);
+        cl[j] = *reinterpret_cast<const u16x8*>(sc_lo + col * PITCH + kq);
+        sl[j] = *reinterpret_cast<const u16x8*>(ss_lo + col * PITCH + kq);
       }
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < 4; ++j) {
         if constexpr (FORM == 0) {
           const bf16x8 a1 = __builtin_bit_cast(bf16x8, ah[i]);
           const bf16x8 a2 = __builtin_bit_cast(bf16x8, al[i]);
@@ -185,8 +201,8 @@ __global__ __launch_bounds__(256) void mfma_teeth_kernel(
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int tooth = t0 + wc * 32 + j * 16 + fr;
+    for (int j = 0; j < 4; ++j) {
+      const int tooth = t0 + j * 16 + fr;
       if (tooth >= k) continue;
       const float rf = ref[tooth];
 #pragma unroll
