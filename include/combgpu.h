@@ -215,6 +215,62 @@ cg_status cg_fit_spectra(cg_plan* plan, const float* y, const float* p0, int64_t
                          int32_t* out_status, float* out_chi2, void* stream);
 
 /*
+ * Learned warm start (CG_FIT_WARM_MLP).  A network 220 -> 256 -> 256 -> 4 with
+ * GELU maps a normalised tooth vector to standardised start parameters
+ * (c, w, d, b); bfloat16 matrix-product operands, FP32 accumulation, biases and
+ * GELU (exact erf) in FP32.  Spectra with K != 220 teeth are resampled
+ * linearly onto 220 points and the predicted centre and width scaled by
+ * (K-1)/219.  The start point is polished by 2 LM iterations; a frame whose
+ * RMS residual sqrt(chi2/(K-4)) then exceeds 2 * noise_floor (or is not
+ * finite) is re-fitted from the cold-start (7x7 median) point with the full
+ * LM and reported with status CG_FIT_FALLBACK.
+ *
+ * Parameters are one host float32 array of CG_MLP_NPARAMS values in the order
+ * W1[256][220], b1[256], W2[256][256], b2[256], W3[4][256], b3[4] (row-major,
+ * out x in).
+ */
+#define CG_MLP_NPARAMS 123396
+
+/* Install trained weights in a plan.  out_mean/out_std (host float32[4]):
+ * p = z * std + mean per output (c, w, d, b).  noise_floor > 0: typical RMS
+ * residual of a converged cold-start fit of this stream. */
+cg_status cg_set_mlp(cg_plan* plan, const float* params, const float* out_mean,
+                     const float* out_std, float noise_floor);
+
+/* Network start points only: y device float32 [n_frames][n_teeth] -> out_p0
+ * device float32 [n_frames][4] (CG_ERR_STATE before cg_set_mlp). */
+cg_status cg_mlp_infer(cg_plan* plan, const float* y, int64_t n_frames, float* out_p0,
+                       void* stream);
+
+/* Training state: FP32 master weights, Adam moments and the buffers of one
+ * mini-batch of `batch` samples (1..65536), on the current device. */
+typedef struct cg_mlp_trainer cg_mlp_trainer;
+cg_status cg_mlp_trainer_create(int32_t batch, const float* init_params /* host */,
+                                cg_mlp_trainer** out);
+cg_status cg_mlp_trainer_destroy(cg_mlp_trainer* trainer);
+
+/*
+ * One Adam step on the mini-batch rows idx[0..batch) (device int32) of
+ *   x        device float32 [*][220] inputs,
+ *   targets  device float32 [*][4] standardised labels,
+ *   weights  device float32 [*] per-sample loss weights (NULL = all 1).
+ * Loss: sum_s w_s sum_j (out_sj - t_sj)^2 / (4 sum_s w_s).  Adam with bias
+ * correction (lr, beta1, beta2, eps).  loss: device float32 [1] or NULL.
+ */
+cg_status cg_mlp_train_step(cg_mlp_trainer* trainer, const float* x, const float* targets,
+                            const float* weights, const int32_t* idx, float lr, float beta1,
+                            float beta2, float eps, float* loss, void* stream);
+
+/* Same forward/backward without the update: grads device float32
+ * [CG_MLP_NPARAMS] (flat layout), loss device float32 [1] or NULL. */
+cg_status cg_mlp_gradients(cg_mlp_trainer* trainer, const float* x, const float* targets,
+                           const float* weights, const int32_t* idx, float* grads, float* loss,
+                           void* stream);
+
+/* Copy the FP32 master weights to the host (synchronises the device). */
+cg_status cg_mlp_get_params(cg_mlp_trainer* trainer, float* params);
+
+/*
  * Tuning knobs of a plan (launch shapes only; results do not depend on them).
  *   CG_TUNE_LM_CHUNK  spectra per wavefront in the fit kernel: 0 = chosen from
  *                     the batch size (default), else a multiple of 4 in 4..256.

@@ -41,6 +41,14 @@ SIGNATURES = {
     "cg_start_points": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_fit_spectra": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp]),
     "cg_set_tuning": (_i32, [_vp, _i32, _i32]),
+    "cg_set_mlp": (_i32, [_vp, _pf32, _pf32, _pf32, _c.c_float]),
+    "cg_mlp_infer": (_i32, [_vp, _vp, _i64, _vp, _vp]),
+    "cg_mlp_trainer_create": (_i32, [_i32, _pf32, _c.POINTER(_vp)]),
+    "cg_mlp_trainer_destroy": (_i32, [_vp]),
+    "cg_mlp_train_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _c.c_float, _c.c_float, _c.c_float,
+                                 _c.c_float, _vp, _vp]),
+    "cg_mlp_gradients": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cg_mlp_get_params": (_i32, [_vp, _pf32]),
     "cg_status_string": (_c.c_char_p, [_i32]),
     "cg_last_error_detail": (_c.c_char_p, []),
     "cg_version": (_c.c_char_p, []),

@@ -8,6 +8,7 @@
 #include <unordered_set>
 
 #include "internal.h"
+#include "mlp.h"
 
 namespace cg {
 
@@ -18,9 +19,11 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t image_bytes(int64_t nf, int k) { return align256((size_t)nf * (size_t)k * sizeof(float)); }
 
-// workspace layout: y image | start points [nf][4]
+// workspace layout: y image | start points [nf][4] | chi2 [nf] | fallback
+// flags [nf] | fallback list [nf] | fallback count
 size_t ws_bytes(int64_t nf, int k) {
-  return image_bytes(nf, k) + align256((size_t)nf * 4 * sizeof(float));
+  return image_bytes(nf, k) + align256((size_t)nf * 4 * sizeof(float)) +
+         3 * align256((size_t)nf * sizeof(float)) + 256;
 }
 
 bool is_pow2(int32_t v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -97,6 +100,7 @@ void free_plan(cg_plan* p) {
     if (b) (void)hipFree(b);
   for (auto* b : p->d_mfma_h)
     if (b) (void)hipFree(b);
+  free_mlp(p->mlp);
   delete p;
 }
 
@@ -243,8 +247,8 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
     cg_status st = cg::mfma_prepare(p, dft);
     if (st != CG_OK) return st;
   }
-  if (fit == CG_FIT_WARM_MLP) {
-    cg::set_detail("learned warm start not available");
+  if (fit == CG_FIT_WARM_MLP && !p->mlp) {
+    cg::set_detail("learned warm start needs cg_set_mlp first");
     return CG_ERR_STATE;
   }
   const hipStream_t s = cg::pick(p, stream);
@@ -264,11 +268,36 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
     ws = static_cast<char*>(p->ws);
   }
   float* y = out_y ? out_y : reinterpret_cast<float*>(ws);
-  float* p0 = reinterpret_cast<float*>(ws + img);
+  char* cur = ws + img;
+  float* p0 = reinterpret_cast<float*>(cur);
+  cur += cg::align256((size_t)nf * 4 * sizeof(float));
+  float* chi2_ws = reinterpret_cast<float*>(cur);
+  cur += cg::align256((size_t)nf * sizeof(float));
+  int32_t* fb_flags = reinterpret_cast<int32_t*>(cur);
+  cur += cg::align256((size_t)nf * sizeof(float));
+  int32_t* fb_idx = reinterpret_cast<int32_t*>(cur);
+  cur += cg::align256((size_t)nf * sizeof(float));
+  int32_t* fb_count = reinterpret_cast<int32_t*>(cur);
   hipError_t e = dft == CG_DFT_FFT ? cg::launch_fft_teeth(p, frames, nf, out_teeth, y, s)
                                    : cg::launch_mfma_teeth(p, dft, frames, nf, out_teeth, y, s);
   if (e != hipSuccess) return hip_fail(e, "tooth transform launch");
   if (fit == CG_FIT_NONE) return CG_OK;
+  if (fit == CG_FIT_WARM_MLP) {
+    float* chi2 = out_chi2 ? out_chi2 : chi2_ws;
+    e = cg::launch_mlp_infer(p->mlp, y, nf, p->k, p0, s);
+    if (e == hipSuccess)
+      e = cg::launch_lm(y, p0, nf, p->k, 2, out_params, out_iters, out_status, chi2, s,
+                        p->lm_chunk);
+    if (e == hipSuccess)
+      e = cg::launch_fallback_select(chi2, nf, p->k, p->mlp->noise_floor, fb_flags, fb_idx,
+                                     fb_count, s);
+    if (e == hipSuccess) e = cg::launch_median_start(y, nf, p->k, nullptr, p0, s, fb_flags);
+    if (e == hipSuccess)
+      e = cg::launch_lm_indexed(y, p0, fb_idx, fb_count, nf, p->k, 20, out_params, out_iters,
+                                out_status, chi2, CG_FIT_FALLBACK, s);
+    if (e != hipSuccess) return hip_fail(e, "warm-start launch");
+    return CG_OK;
+  }
   e = cg::launch_median_start(y, nf, p->k, nullptr, p0, s);
   if (e != hipSuccess) return hip_fail(e, "median/start launch");
   e = cg::launch_lm(y, p0, nf, p->k, 20, out_params, out_iters, out_status, out_chi2, s,
@@ -355,6 +384,87 @@ cg_status cg_fit_spectra(cg_plan* p, const float* y, const float* p0, int64_t nf
   hipError_t e = cg::launch_lm(y, p0, nf, p->k, max_iter, out_params, out_iters, out_status,
                                out_chi2, s, p->lm_chunk);
   if (e != hipSuccess) return hip_fail(e, "lm launch");
+  return CG_OK;
+}
+
+cg_status cg_set_mlp(cg_plan* p, const float* params, const float* out_mean, const float* out_std,
+                     float noise_floor) {
+  if (!p || !params || !out_mean || !out_std) return CG_ERR_NULL;
+  for (int i = 0; i < CG_MLP_NPARAMS; ++i)
+    if (!std::isfinite(params[i])) {
+      cg::set_detail("network parameters must be finite");
+      return CG_ERR_INVALID_ARG;
+    }
+  for (int j = 0; j < 4; ++j)
+    if (!std::isfinite(out_mean[j]) || !std::isfinite(out_std[j]) || !(out_std[j] > 0.f)) {
+      cg::set_detail("output mean must be finite and std finite and > 0");
+      return CG_ERR_INVALID_ARG;
+    }
+  if (!std::isfinite(noise_floor) || !(noise_floor > 0.f)) {
+    cg::set_detail("noise_floor must be finite and > 0");
+    return CG_ERR_INVALID_ARG;
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "cg_set_mlp sync");
+  cg_mlp* m = nullptr;
+  cg_status st = cg::make_mlp(params, out_mean, out_std, noise_floor, &m);
+  if (st != CG_OK) return st;
+  cg::free_mlp(p->mlp);
+  p->mlp = m;
+  return CG_OK;
+}
+
+cg_status cg_mlp_infer(cg_plan* p, const float* y, int64_t nf, float* out_p0, void* stream) {
+  if (!p || !out_p0) return CG_ERR_NULL;
+  if (nf < 0) return CG_ERR_INVALID_ARG;
+  if (!p->mlp) return CG_ERR_STATE;
+  if (nf == 0) return CG_OK;
+  if (!y) return CG_ERR_NULL;
+  hipError_t e = cg::launch_mlp_infer(p->mlp, y, nf, p->k, out_p0, cg::pick(p, stream));
+  if (e != hipSuccess) return hip_fail(e, "mlp launch");
+  return CG_OK;
+}
+
+cg_status cg_mlp_trainer_create(int32_t batch, const float* init, cg_mlp_trainer** out) {
+  if (!out) return CG_ERR_NULL;
+  *out = nullptr;
+  if (!init) return CG_ERR_NULL;
+  if (batch < 1 || batch > 65536) return CG_ERR_INVALID_ARG;
+  for (int i = 0; i < CG_MLP_NPARAMS; ++i)
+    if (!std::isfinite(init[i])) return CG_ERR_INVALID_ARG;
+  return cg::make_trainer(batch, init, out);
+}
+
+cg_status cg_mlp_trainer_destroy(cg_mlp_trainer* t) {
+  cg::free_trainer(t);
+  return CG_OK;
+}
+
+cg_status cg_mlp_train_step(cg_mlp_trainer* t, const float* x, const float* targets,
+                            const float* weights, const int32_t* idx, float lr, float beta1,
+                            float beta2, float eps, float* loss, void* stream) {
+  if (!t || !x || !targets || !idx) return CG_ERR_NULL;
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return CG_ERR_INVALID_ARG;
+  return cg::trainer_step(t, x, targets, weights, idx, lr, beta1, beta2, eps, 1, nullptr, loss,
+                          reinterpret_cast<hipStream_t>(stream));
+}
+
+cg_status cg_mlp_gradients(cg_mlp_trainer* t, const float* x, const float* targets,
+                           const float* weights, const int32_t* idx, float* grads, float* loss,
+                           void* stream) {
+  if (!t || !x || !targets || !idx || !grads) return CG_ERR_NULL;
+  return cg::trainer_step(t, x, targets, weights, idx, 1.f, 0.f, 0.f, 1.f, 0, grads, loss,
+                          reinterpret_cast<hipStream_t>(stream));
+}
+
+cg_status cg_mlp_get_params(cg_mlp_trainer* t, float* params) {
+  if (!t || !params) return CG_ERR_NULL;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = hipMemcpy(params, t->params, sizeof(float) * CG_MLP_NPARAMS, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "cg_mlp_get_params");
   return CG_OK;
 }
 

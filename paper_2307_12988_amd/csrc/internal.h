@@ -57,8 +57,10 @@ hipError_t launch_column_mean(const float* mags, int64_t n, int k, float* out, h
 
 // A4: 7x7 median image (out_m, may be null) and/or start points (out_p0, may
 // be null) from normalised spectra, in one kernel.
+// flags (may be null): only frames with flags[f] != 0 get a start point, and
+// blocks without such frames return at once.
 hipError_t launch_median_start(const float* y, int64_t n_frames, int k, float* out_m,
-                               float* out_p0, hipStream_t s);
+                               float* out_p0, hipStream_t s, const int32_t* flags = nullptr);
 // Start points from a given median image.
 hipError_t launch_start_points(const float* m, int64_t n_frames, int k, float* out_p0,
                                hipStream_t s);
@@ -69,5 +71,15 @@ int lm_chunk(int64_t n_frames);
 hipError_t launch_lm(const float* y, const float* p0, int64_t n_frames, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
                      int chunk = 0);
+// Indexed form: fit frames idx[0..*count) (count read on the device, at most
+// n_cap); every reported status is replaced by status_code.
+hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx,
+                             const int32_t* count, int64_t n_cap, int k, int max_iter,
+                             float* params, int32_t* iters, int32_t* status, float* chi2,
+                             int32_t status_code, hipStream_t s);
+// Warm-start fallback selection: flags[f] = 1 and f appended to idx when the
+// polished fit's RMS residual exceeds 2 * noise_floor or is not finite.
+hipError_t launch_fallback_select(const float* chi2, int64_t n_frames, int k, float noise_floor,
+                                  int32_t* flags, int32_t* idx, int32_t* count, hipStream_t s);
 
 }  // namespace cg

@@ -157,19 +157,26 @@ __device__ __forceinline__ void load_spectrum(const float* __restrict__ y, int64
 
 template <int Q>
 __global__ __launch_bounds__(256) void lm_kernel(const float* __restrict__ y,
-                                                 const float* __restrict__ p0, int64_t nf, int k,
-                                                 int max_iter, int chunk,
+                                                 const float* __restrict__ p0,
+                                                 const int32_t* __restrict__ idx,
+                                                 const int32_t* __restrict__ count, int64_t nf,
+                                                 int k, int max_iter, int chunk,
                                                  float* __restrict__ params,
                                                  int32_t* __restrict__ iters,
                                                  int32_t* __restrict__ status,
-                                                 float* __restrict__ chi2_out) {
+                                                 float* __restrict__ chi2_out, int status_code) {
   const int lane = lane_id();
   const int grp = lane >> 4;
   const int gl = lane & 15;
   const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t base = wave * chunk;
-  if (base >= nf) return;
-  const int64_t end = base + chunk < nf ? base + chunk : nf;
+  int64_t n = nf;
+  if (count) {
+    const int64_t c = *count;
+    n = c < nf ? (c < 0 ? 0 : c) : nf;
+  }
+  if (base >= n) return;
+  const int64_t end = base + chunk < n ? base + chunk : n;
 
   int64_t s = base + grp;  // spectrum of this group (>= end: idle)
   int64_t next = base + 4;  // wave-uniform hand-out index
@@ -178,13 +185,15 @@ __global__ __launch_bounds__(256) void lm_kernel(const float* __restrict__ y,
   float yv[Q];
   double c = 0, w = 1, d = 0, b = 0, lam = 1e-3;
   int it = 0;
+  int64_t fi = 0;  // frame of the current spectrum
   Sums cur;
   if (active) {
-    load_spectrum<Q>(y, s, k, yv);
-    c = p0[s * 4 + 0];
-    w = p0[s * 4 + 1];
-    d = p0[s * 4 + 2];
-    b = p0[s * 4 + 3];
+    fi = idx ? (int64_t)idx[s] : s;
+    load_spectrum<Q>(y, fi, k, yv);
+    c = p0[fi * 4 + 0];
+    w = p0[fi * 4 + 1];
+    d = p0[fi * 4 + 2];
+    b = p0[fi * 4 + 3];
   } else {
 #pragma unroll
     for (int q = 0; q < Q; ++q) yv[q] = 0.0f;
@@ -247,14 +256,14 @@ __global__ __launch_bounds__(256) void lm_kernel(const float* __restrict__ y,
     // 4. finished groups report and take the next spectrum of the chunk
     if (done && gl == 0) {
       if (params) {
-        params[s * 4 + 0] = (float)c;
-        params[s * 4 + 1] = (float)w;
-        params[s * 4 + 2] = (float)d;
-        params[s * 4 + 3] = (float)b;
+        params[fi * 4 + 0] = (float)c;
+        params[fi * 4 + 1] = (float)w;
+        params[fi * 4 + 2] = (float)d;
+        params[fi * 4 + 3] = (float)b;
       }
-      if (iters) iters[s] = it;
-      if (status) status[s] = st;
-      if (chi2_out) chi2_out[s] = (float)cur.chi2;
+      if (iters) iters[fi] = it;
+      if (status) status[fi] = status_code >= 0 ? status_code : st;
+      if (chi2_out) chi2_out[fi] = (float)cur.chi2;
     }
     const uint64_t fin = __ballot(done && gl == 0);
     if (fin != 0ull) {
@@ -264,11 +273,12 @@ __global__ __launch_bounds__(256) void lm_kernel(const float* __restrict__ y,
         active = s < end;
         fresh = true;
         if (active) {
-          load_spectrum<Q>(y, s, k, yv);
-          c = p0[s * 4 + 0];
-          w = p0[s * 4 + 1];
-          d = p0[s * 4 + 2];
-          b = p0[s * 4 + 3];
+          fi = idx ? (int64_t)idx[s] : s;
+          load_spectrum<Q>(y, fi, k, yv);
+          c = p0[fi * 4 + 0];
+          w = p0[fi * 4 + 1];
+          d = p0[fi * 4 + 2];
+          b = p0[fi * 4 + 3];
         }
       }
       next += __popcll(fin);
@@ -276,7 +286,33 @@ __global__ __launch_bounds__(256) void lm_kernel(const float* __restrict__ y,
   }
 }
 
+__global__ void zero_i32_kernel(int32_t* p) { *p = 0; }
+
+__global__ void fallback_select_kernel(const float* __restrict__ chi2, int64_t nf, int k,
+                                       float thr2, int32_t* __restrict__ flags,
+                                       int32_t* __restrict__ idx, int32_t* __restrict__ count) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  // RMS residual sqrt(chi2 / (k - 4)) > 2 sigma  <=>  chi2 > 4 sigma^2 (k - 4)
+  const float c = chi2[f];
+  const bool bad = !isfinite(c) || c > thr2;
+  flags[f] = bad ? 1 : 0;
+  if (bad) idx[atomicAdd(count, 1)] = (int32_t)f;
+}
+
 }  // namespace
+
+hipError_t launch_fallback_select(const float* chi2, int64_t nf, int k, float noise_floor,
+                                  int32_t* flags, int32_t* idx, int32_t* count, hipStream_t s) {
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, count);
+  const double dof = k > 4 ? (double)(k - 4) : 1.0;
+  const float thr2 = (float)(4.0 * (double)noise_floor * (double)noise_floor * dof);
+  const int64_t blocks = (nf + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fallback_select_kernel, dim3((unsigned)blocks), dim3(256), 0, s, chi2, nf, k,
+                     thr2, flags, idx, count);
+  return hipGetLastError();
+}
 
 int lm_chunk(int64_t nf) {
   // spectra per wave: enough waves to fill 256 CUs several times over, and at
@@ -296,7 +332,22 @@ hipError_t launch_lm(const float* y, const float* p0, int64_t nf, int k, int max
   const int64_t blocks = (waves + 3) / 4;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   CG_DISPATCH_Q16(k, hipLaunchKernelGGL(lm_kernel<Q>, dim3((unsigned)blocks), dim3(256), 0, s, y,
-                                        p0, nf, k, max_iter, chunk, params, iters, status, chi2));
+                                        p0, nullptr, nullptr, nf, k, max_iter, chunk, params,
+                                        iters, status, chi2, -1));
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx,
+                             const int32_t* count, int64_t n_cap, int k, int max_iter,
+                             float* params, int32_t* iters, int32_t* status, float* chi2,
+                             int32_t status_code, hipStream_t s) {
+  const int chunk = 4;  // the count is only known on the device: small chunks keep waves busy
+  const int64_t waves = (n_cap + chunk - 1) / chunk;
+  const int64_t blocks = (waves + 3) / 4;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  CG_DISPATCH_Q16(k, hipLaunchKernelGGL(lm_kernel<Q>, dim3((unsigned)blocks), dim3(256), 0, s, y,
+                                        p0, idx, count, n_cap, k, max_iter, chunk, params, iters,
+                                        status, chi2, status_code));
   return hipGetLastError();
 }
 

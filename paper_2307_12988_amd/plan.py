@@ -25,6 +25,8 @@ FIT_NONE = 0x20
 
 FIT_CONVERGED, FIT_MAX_ITER, FIT_SINGULAR, FIT_FALLBACK = 0, 1, 2, 3
 TUNE_LM_CHUNK = 1
+MLP_NPARAMS = 123396
+MLP_IN = 220
 
 
 def _dev_ptr(t, dtype, shape, name):
@@ -205,6 +207,30 @@ class Plan:
         _lib.check(st, "cg_init_spectra")
         return p0, med
 
+    def set_mlp(self, params, out_mean, out_std, noise_floor: float):
+        """Install warm-start weights (flat float32 [MLP_NPARAMS])."""
+        prm = np.ascontiguousarray(np.asarray(params), dtype=np.float32)
+        if prm.shape != (MLP_NPARAMS,):
+            raise ValueError(f"params must have {MLP_NPARAMS} values")
+        mean = np.ascontiguousarray(np.asarray(out_mean), dtype=np.float32)
+        std = np.ascontiguousarray(np.asarray(out_std), dtype=np.float32)
+        if mean.shape != (4,) or std.shape != (4,):
+            raise ValueError("out_mean and out_std must have 4 values")
+        st = self._lib.cg_set_mlp(self._h, prm.ctypes.data_as(_lib._pf32),
+                                  mean.ctypes.data_as(_lib._pf32), std.ctypes.data_as(_lib._pf32),
+                                  float(noise_floor))
+        _lib.check(st, "cg_set_mlp")
+
+    def mlp_infer(self, y, out=None):
+        nf = int(y.shape[0])
+        yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")
+        if out is None:
+            out = torch.empty((nf, 4), dtype=torch.float32, device=y.device)
+        st = self._lib.cg_mlp_infer(self._h, yp, nf, _dev_ptr(out, torch.float32, (nf, 4), "p0"),
+                                    _stream(y.device))
+        _lib.check(st, "cg_mlp_infer")
+        return out
+
     def median_filter(self, y, out=None):
         nf = int(y.shape[0])
         yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")
@@ -248,3 +274,63 @@ class Plan:
                                       ctypes.c_void_p(chi2.data_ptr()), _stream(dev))
         _lib.check(st, "cg_fit_spectra")
         return params, iters, status, chi2
+
+
+class Trainer:
+    """Training state of the warm-start network (FP32 master weights, Adam
+    moments, mini-batch buffers) on the GPU; every step runs in the library's
+    kernels."""
+
+    def __init__(self, batch: int, init_params):
+        self._lib = _lib.load()
+        init = np.ascontiguousarray(np.asarray(init_params), dtype=np.float32)
+        if init.shape != (MLP_NPARAMS,):
+            raise ValueError(f"init_params must have {MLP_NPARAMS} values")
+        h = ctypes.c_void_p()
+        st = self._lib.cg_mlp_trainer_create(int(batch), init.ctypes.data_as(_lib._pf32),
+                                             ctypes.byref(h))
+        _lib.check(st, "cg_mlp_trainer_create")
+        self._h = h
+        self.batch = int(batch)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.cg_mlp_trainer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _args(self, x, targets, weights, idx):
+        n = int(x.shape[0])
+        xp = _dev_ptr(x, torch.float32, (n, MLP_IN), "x")
+        tp = _dev_ptr(targets, torch.float32, (n, 4), "targets")
+        wp = _dev_ptr(weights, torch.float32, (n,), "weights") if weights is not None else None
+        ip = _dev_ptr(idx, torch.int32, (self.batch,), "idx")
+        return xp, tp, wp, ip
+
+    def step(self, x, targets, weights, idx, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+             loss=None):
+        xp, tp, wp, ip = self._args(x, targets, weights, idx)
+        lp = _dev_ptr(loss, torch.float32, (1,), "loss") if loss is not None else None
+        st = self._lib.cg_mlp_train_step(self._h, xp, tp, wp, ip, float(lr), float(beta1),
+                                         float(beta2), float(eps), lp, _stream(x.device))
+        _lib.check(st, "cg_mlp_train_step")
+
+    def gradients(self, x, targets, weights, idx):
+        xp, tp, wp, ip = self._args(x, targets, weights, idx)
+        g = torch.empty((MLP_NPARAMS,), dtype=torch.float32, device=x.device)
+        loss = torch.empty((1,), dtype=torch.float32, device=x.device)
+        st = self._lib.cg_mlp_gradients(self._h, xp, tp, wp, ip, ctypes.c_void_p(g.data_ptr()),
+                                        ctypes.c_void_p(loss.data_ptr()), _stream(x.device))
+        _lib.check(st, "cg_mlp_gradients")
+        return g, loss
+
+    def params(self):
+        out = np.empty(MLP_NPARAMS, dtype=np.float32)
+        _lib.check(self._lib.cg_mlp_get_params(self._h, out.ctypes.data_as(_lib._pf32)),
+                   "cg_mlp_get_params")
+        return out
