@@ -198,6 +198,116 @@ def precision_forms(args, torch, cg, dev):
     plan.close()
 
 
+def multistream(args, torch, cg, dev):
+    """16 concurrent streams (frame lengths 512..8192, 64..440 teeth, own
+    reference, dip parameters and noise floor) through the ring pipeline with
+    the learned warm start.  Phase 1: producer at maximum rate with
+    backpressure (consumption capacity).  Phase 2: every stream paced at its
+    digitiser rate (1.1 GS/s of int16 = 2.2 GB/s each), bursts dropped and
+    counted when the ring is full; latency percentiles from this phase."""
+    specs = synth.spec_multistream(seed=100)
+    weights = os.path.join(ROOT, "paper_2307_12988_amd", "data", "warmstart_learned.npz")
+    w = np.load(weights)
+    pool_frames = 8192
+    _log(f"generating {len(specs)} stream pools of {pool_frames} frames ...")
+    jobs = [(sp, pool_frames, 100 + i, 0) for i, sp in enumerate(specs)]
+    with cf.ProcessPoolExecutor(max_workers=8) as ex:
+        gen = list(ex.map(_gen, jobs))
+    plans, pools, fl = [], [], []
+    tune = {}
+    for i, (sp, (_, frames, ref_frames)) in enumerate(zip(specs, gen)):
+        pl = cg.Plan(sp.n, sp.fs, sp.bins, np.ones(sp.k, dtype=np.float32))
+        pl.set_reference(pl.reference_from_frames(torch.from_numpy(ref_frames).to(dev)).cpu().numpy())
+        pool = torch.from_numpy(frames).to(dev)
+        # per-stream noise floor from a cold-start calibration batch (host median)
+        cal = pl.process(pool[:2048], want=("status", "chi2"))
+        c2 = cal["chi2"].cpu().numpy().astype(np.float64)
+        ok = cal["status"].cpu().numpy() == 0
+        noise = float(np.median(np.sqrt(np.maximum(c2[ok], 0) / (sp.k - 4))))
+        pl.set_mlp(w["params"], w["out_mean"], w["out_std"], noise)
+        chunk, ms = pl.autotune(pool[:4096], flags=cg.FIT_WARM_MLP)
+        tune[i] = {"n": sp.n, "k": sp.k, "lm_chunk": chunk, "ms_4096": ms, "noise_floor": noise}
+        plans.append(pl)
+        pools.append(pool)
+        fl.append(cg.FIT_WARM_MLP)
+    torch.cuda.synchronize(dev)
+    pipe = cg.Pipeline(plans, fl, slots_per_stream=args.slots, max_burst_frames=4096)
+    rng = np.random.default_rng(7)
+    ns = len(specs)
+
+    def burst(i):
+        n = int(rng.integers(256, 4097))
+        off = int(rng.integers(0, pool_frames - n + 1))
+        return pools[i][off:off + n]
+
+    seq = [0] * ns
+    # phase 1: maximum rate with backpressure
+    t_end = time.perf_counter() + args.phase1
+    full = 0
+    while time.perf_counter() < t_end:
+        for i in rng.permutation(ns):
+            if rng.random() < 0.2:
+                continue  # random skips interleave the streams unevenly
+            try:
+                pipe.put(int(i), burst(int(i)), seq[i])
+                seq[i] += 1
+            except cg.RingFull:
+                full += 1
+    pipe.drain(120000)
+    s1 = pipe.stats()
+    pipe.close()
+    # phase 2: paced at the digitiser rate of every stream
+    pipe = cg.Pipeline(plans, fl, slots_per_stream=args.slots, max_burst_frames=4096)
+    t0 = time.perf_counter()
+    due = [t0 + float(rng.random()) * 1e-3 for _ in range(ns)]
+    nxt = [burst(i) for i in range(ns)]
+    dropped = 0
+    last_log = t0
+    while True:
+        now = time.perf_counter()
+        if now - t0 >= args.seconds:
+            break
+        i = int(np.argmin(due))
+        if due[i] > now:
+            continue
+        b = nxt[i]
+        try:
+            pipe.put(i, b, seq[i])
+            seq[i] += 1
+        except cg.RingFull:
+            dropped += 1
+        due[i] += b.shape[0] * specs[i].n / specs[i].fs
+        nxt[i] = burst(i)
+        if now - last_log > 30:
+            _log(f"  {now - t0:.0f} s: {pipe.stats()['bursts']:.0f} bursts")
+            last_log = now
+    pipe.drain(120000)
+    s2 = pipe.stats()
+    pipe.close()
+    offered = sum(2.0 * sp.fs for sp in specs)
+    line = {
+        "metric": METRIC, "value": s1["bytes_per_s"] / 1e9, "unit": "GB/s", "n_gpus": 1,
+        "steps": int(s1["bursts"]), "warmup": 0,
+        "ms_per_step": 1e3 * s1["seconds"] / max(1.0, s1["bursts"]),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{ns} interleaved streams, frame lengths 512-8192, 64-440 teeth, "
+                               f"bursts of 256-4096 frames, learned warm start, ring pipeline",
+                   "streams": ns, "slots_per_stream": args.slots},
+        "spectra_per_s": s1["frames_per_s"],
+        "phase1_max_rate": {k: s1[k] for k in s1}, "phase1_ring_full_events": full,
+        "phase2_paced": {"seconds": args.seconds, "offered_GBps": offered / 1e9,
+                         "achieved_GBps": s2["bytes_per_s"] / 1e9, "dropped_bursts": dropped,
+                         "overflows": s2["overflows"], "lat_p50_ms": s2["lat_p50_ms"],
+                         "lat_p99_ms": s2["lat_p99_ms"], "lat_max_ms": s2["lat_max_ms"],
+                         "bursts": s2["bursts"]},
+        "autotune": tune,
+    }
+    print(json.dumps(line), flush=True)
+    for pl in plans:
+        pl.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,9 +317,16 @@ def main():
     ap.add_argument("--frames", type=int, default=65536)
     ap.add_argument("--cpu-frames", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["paper_rate", "precision"], default="paper_rate",
+    ap.add_argument("--workload", choices=["paper_rate", "precision", "multistream"],
+                    default="paper_rate",
                     help="paper_rate: the headline line; precision: 131072 x 4096 frames, one "
-                         "line per tooth-DFT form (FFT and the three matrix-core forms)")
+                         "line per tooth-DFT form (FFT and the three matrix-core forms); "
+                         "multistream: 16 interleaved streams through the ring pipeline")
+    ap.add_argument("--seconds", type=float, default=20.0,
+                    help="multistream: length of the paced phase (600 for the 10-minute run)")
+    ap.add_argument("--phase1", type=float, default=5.0,
+                    help="multistream: length of the maximum-rate phase")
+    ap.add_argument("--slots", type=int, default=8, help="multistream: ring slots per stream")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference for "
                          "the HBM byte counters)")
@@ -236,6 +353,8 @@ def main():
         return
     if args.workload == "precision":
         return precision_forms(args, torch, cg, dev)
+    if args.workload == "multistream":
+        return multistream(args, torch, cg, dev)
     spec = synth.spec_paper_rate()
     nf, n, k = args.frames, spec.n, spec.k
     _log(f"generating {args.pool} batches of {nf} x {n} int16 ...")

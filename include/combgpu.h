@@ -54,6 +54,7 @@ typedef int32_t cg_status;
 #define CG_ERR_HIP         (-6) /* HIP runtime / launch error (see detail)      */
 #define CG_ERR_WORKSPACE   (-7) /* caller workspace smaller than required       */
 #define CG_ERR_STATE       (-8) /* operation needs state the plan lacks         */
+#define CG_ERR_RING_FULL   (-9) /* pipeline: no free slot; the burst was not taken */
 
 /* Per-frame fit status written to out_status. */
 #define CG_FIT_CONVERGED 0 /* accepted step lowered chi2 by <= 1e-6 chi2        */
@@ -278,6 +279,74 @@ cg_status cg_mlp_get_params(cg_mlp_trainer* trainer, float* params);
  */
 #define CG_TUNE_LM_CHUNK 1
 cg_status cg_set_tuning(cg_plan* plan, int32_t knob, int32_t value);
+
+/*
+ * Multi-stream ring pipeline (paper: ring buffer between digitiser and GPU,
+ * asynchronous batches across threads, out-of-order completion re-sorted into
+ * time order; indefinite streaming only while consumption keeps up, otherwise
+ * the buffer overflows).
+ *
+ * Each of n_streams streams (<= CG_PIPE_MAX_STREAMS) has its own plan (frame
+ * length, teeth, reference, network) and fit form (CG_FIT_COLD or
+ * CG_FIT_WARM_MLP) and slots_per_stream device slots of max_burst_frames
+ * frames.  Each slot's processing chain is captured once as a hipGraph; a
+ * persistent dispatcher thread launches published bursts in publish order on
+ * one HIP stream per stream (default priority) and records the host-clock
+ * latency from publish to results in pinned host memory.  Plans must outlive
+ * the pipeline and must not change while it exists.
+ *
+ * options: CG_PIPE_KEEP_RESULTS keeps each completed burst's results (and its
+ * slot) until cg_pipeline_read; without it slots are recycled on completion.
+ * CG_PIPE_DRY_RUN simulates the bookkeeping without a device (plans and
+ * fit_flags may be NULL): a burst completes dry_us_per_frame * n us after it
+ * was published and acquire returns no frame buffer.
+ */
+typedef struct cg_pipeline cg_pipeline;
+#define CG_PIPE_MAX_STREAMS  64
+#define CG_PIPE_KEEP_RESULTS 0x1u
+#define CG_PIPE_DRY_RUN      0x2u
+cg_status cg_pipeline_create(int32_t n_streams, cg_plan* const* plans, const uint32_t* fit_flags,
+                             int32_t slots_per_stream, int32_t max_burst_frames,
+                             uint32_t options, double dry_us_per_frame, cg_pipeline** out);
+/* Stops the dispatcher after the queued bursts completed, frees everything. */
+cg_status cg_pipeline_destroy(cg_pipeline* pipe);
+/* Take a free slot of `stream` for writing: *frames receives its device buffer
+ * int16 [max_burst_frames][frame_len].  CG_ERR_RING_FULL (counted as an
+ * overflow) when every slot is queued, running or holding unread results. */
+cg_status cg_pipeline_acquire(cg_pipeline* pipe, int32_t stream, int32_t* slot,
+                              int16_t** frames);
+/* Hand a written slot to the dispatcher: n_frames in 1..max_burst_frames,
+ * seq the caller's sequence number for this stream (increasing). */
+cg_status cg_pipeline_publish(cg_pipeline* pipe, int32_t stream, int32_t slot, int32_t n_frames,
+                              int64_t seq);
+/* Acquire + copy + publish in one call: src holds n_frames frames of the
+ * stream's frame length in host or device memory (any address HIP can copy
+ * from; the copy is queued on the stream's HIP stream ahead of the burst, so
+ * a host source must stay unchanged until the burst completes and is best
+ * pinned).  CG_ERR_RING_FULL as for cg_pipeline_acquire. */
+cg_status cg_pipeline_put(cg_pipeline* pipe, int32_t stream, const int16_t* src, int32_t n_frames,
+                          int64_t seq);
+/* Pop the oldest completed burst of `stream` (CG_PIPE_KEEP_RESULTS): params
+ * host float32 [n][4], status host int32 [n] (either may be NULL), capacity in
+ * frames; CG_ERR_STATE when none is ready or the order was violated. */
+cg_status cg_pipeline_read(cg_pipeline* pipe, int32_t stream, float* params, int32_t* status,
+                           int32_t capacity, int32_t* n_frames, int64_t* seq);
+/* Wait until every published burst has completed (CG_ERR_STATE on timeout). */
+cg_status cg_pipeline_drain(cg_pipeline* pipe, int32_t timeout_ms);
+/* Counters since creation, out[CG_PIPE_NSTATS]: bursts, frames, bytes of
+ * int16 input, overflows, seconds from first publish to last completion,
+ * latency p50, p99, max (ms), bytes/s, frames/s. */
+#define CG_PIPE_NSTATS 10
+cg_status cg_pipeline_stats(cg_pipeline* pipe, double* out, int32_t n_out);
+
+/*
+ * Autotuner: times the whole path (flags as for cg_process_batch_ex) on the
+ * given frames for each fit-kernel launch shape (spectra per wavefront 4, 8,
+ * 16, 32, 64), installs the fastest in the plan and returns it (*chosen) and
+ * its time per batch (*best_ms, may be NULL).  Synchronises the device.
+ */
+cg_status cg_autotune(cg_plan* plan, const int16_t* frames, int64_t n_frames, uint32_t flags,
+                      void* workspace, size_t workspace_bytes, int32_t* chosen, float* best_ms);
 
 /* Static description of a status code. */
 const char* cg_status_string(cg_status status);

@@ -49,6 +49,15 @@ SIGNATURES = {
                                  _c.c_float, _vp, _vp]),
     "cg_mlp_gradients": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cg_mlp_get_params": (_i32, [_vp, _pf32]),
+    "cg_pipeline_create": (_i32, [_i32, _vp, _vp, _i32, _i32, _u32, _dbl, _c.POINTER(_vp)]),
+    "cg_pipeline_destroy": (_i32, [_vp]),
+    "cg_pipeline_acquire": (_i32, [_vp, _i32, _pi32, _c.POINTER(_vp)]),
+    "cg_pipeline_publish": (_i32, [_vp, _i32, _i32, _i32, _i64]),
+    "cg_pipeline_put": (_i32, [_vp, _i32, _vp, _i32, _i64]),
+    "cg_pipeline_read": (_i32, [_vp, _i32, _pf32, _pi32, _i32, _pi32, _c.POINTER(_i64)]),
+    "cg_pipeline_drain": (_i32, [_vp, _i32]),
+    "cg_pipeline_stats": (_i32, [_vp, _c.POINTER(_dbl), _i32]),
+    "cg_autotune": (_i32, [_vp, _vp, _i64, _u32, _vp, _sz, _pi32, _pf32]),
     "cg_status_string": (_c.c_char_p, [_i32]),
     "cg_last_error_detail": (_c.c_char_p, []),
     "cg_version": (_c.c_char_p, []),

@@ -130,6 +130,7 @@ const char* cg_status_string(cg_status s) {
     case CG_ERR_HIP: return "HIP runtime error";
     case CG_ERR_WORKSPACE: return "workspace too small";
     case CG_ERR_STATE: return "plan lacks the state this operation needs";
+    case CG_ERR_RING_FULL: return "ring full: burst not taken (overflow)";
     default: return "unknown status";
   }
 }

@@ -138,13 +138,17 @@ template <int LOGM>
 __global__ __launch_bounds__(256) void fft_teeth_kernel(
     const int32_t* __restrict__ frames, int64_t n_frames, const int32_t* __restrict__ bins,
     const float* __restrict__ ref, const c32* __restrict__ tw, int k_teeth,
-    float* __restrict__ out_mag, float* __restrict__ out_y) {
+    float* __restrict__ out_mag, float* __restrict__ out_y, const int32_t* __restrict__ dev_n) {
   using S = FftShape<LOGM>;
   constexpr int M = S::M, T = S::T, FPB = S::FPB, PM = S::PM, R3 = S::R3;
   constexpr int N = 2 * M;
   __shared__ float s_re[FPB * PM];
   __shared__ float s_im[FPB * PM];
 
+  if (dev_n) {
+    const int64_t dn = *dev_n;
+    n_frames = dn < n_frames ? dn : n_frames;
+  }
   const int tid = threadIdx.x;
   const int fl = tid / T;
   const int j = tid - fl * T;
@@ -243,26 +247,26 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 
 template <int LOGM>
 hipError_t launch_t(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
-                    float* out_y, hipStream_t s) {
+                    float* out_y, hipStream_t s, const int32_t* dev_n) {
   using S = FftShape<LOGM>;
   const int64_t blocks = (nf + S::FPB - 1) / S::FPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fft_teeth_kernel<LOGM>, dim3((unsigned)blocks), dim3(256), 0, s,
                      reinterpret_cast<const int32_t*>(frames), nf, p->d_bins, p->d_ref,
-                     reinterpret_cast<const c32*>(p->d_tw), p->k, out_mag, out_y);
+                     reinterpret_cast<const c32*>(p->d_tw), p->k, out_mag, out_y, dev_n);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_fft_teeth(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
-                            float* out_y, hipStream_t s) {
+                            float* out_y, hipStream_t s, const int32_t* dev_n) {
   switch (p->m) {
-    case 256: return launch_t<8>(p, frames, nf, out_mag, out_y, s);
-    case 512: return launch_t<9>(p, frames, nf, out_mag, out_y, s);
-    case 1024: return launch_t<10>(p, frames, nf, out_mag, out_y, s);
-    case 2048: return launch_t<11>(p, frames, nf, out_mag, out_y, s);
-    case 4096: return launch_t<12>(p, frames, nf, out_mag, out_y, s);
+    case 256: return launch_t<8>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 512: return launch_t<9>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 1024: return launch_t<10>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 2048: return launch_t<11>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 4096: return launch_t<12>(p, frames, nf, out_mag, out_y, s, dev_n);
     default: return hipErrorInvalidValue;
   }
 }

@@ -43,8 +43,12 @@ cg_status hip_fail(hipError_t e, const char* where);
 void set_detail(const std::string& s);
 
 // A1-A3: int16 frames -> raw tooth amplitudes and/or normalised spectra.
+// Every launch helper takes an optional dev_n: a device int32 frame count
+// read by the kernels at run time (at most n_frames, the capacity the grid is
+// sized for), so one captured graph serves bursts of any size.
 hipError_t launch_fft_teeth(const cg_plan* p, const int16_t* frames, int64_t n_frames,
-                            float* out_mag, float* out_y, hipStream_t s);
+                            float* out_mag, float* out_y, hipStream_t s,
+                            const int32_t* dev_n = nullptr);
 
 // A6: tooth DFT on the matrix cores (form = CG_DFT_MFMA_*); mfma_prepare
 // builds the plan's basis for the form on first use.
@@ -60,7 +64,8 @@ hipError_t launch_column_mean(const float* mags, int64_t n, int k, float* out, h
 // flags (may be null): only frames with flags[f] != 0 get a start point, and
 // blocks without such frames return at once.
 hipError_t launch_median_start(const float* y, int64_t n_frames, int k, float* out_m,
-                               float* out_p0, hipStream_t s, const int32_t* flags = nullptr);
+                               float* out_p0, hipStream_t s, const int32_t* flags = nullptr,
+                               const int32_t* dev_n = nullptr);
 // Start points from a given median image.
 hipError_t launch_start_points(const float* m, int64_t n_frames, int k, float* out_p0,
                                hipStream_t s);
@@ -70,7 +75,7 @@ hipError_t launch_start_points(const float* m, int64_t n_frames, int k, float* o
 int lm_chunk(int64_t n_frames);
 hipError_t launch_lm(const float* y, const float* p0, int64_t n_frames, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
-                     int chunk = 0);
+                     int chunk = 0, const int32_t* dev_n = nullptr);
 // Indexed form: fit frames idx[0..*count) (count read on the device, at most
 // n_cap); every reported status is replaced by status_code.
 hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx,
@@ -80,6 +85,7 @@ hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx
 // Warm-start fallback selection: flags[f] = 1 and f appended to idx when the
 // polished fit's RMS residual exceeds 2 * noise_floor or is not finite.
 hipError_t launch_fallback_select(const float* chi2, int64_t n_frames, int k, float noise_floor,
-                                  int32_t* flags, int32_t* idx, int32_t* count, hipStream_t s);
+                                  int32_t* flags, int32_t* idx, int32_t* count, hipStream_t s,
+                                  const int32_t* dev_n = nullptr);
 
 }  // namespace cg

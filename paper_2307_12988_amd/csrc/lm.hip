@@ -290,8 +290,13 @@ __global__ void zero_i32_kernel(int32_t* p) { *p = 0; }
 
 __global__ void fallback_select_kernel(const float* __restrict__ chi2, int64_t nf, int k,
                                        float thr2, int32_t* __restrict__ flags,
-                                       int32_t* __restrict__ idx, int32_t* __restrict__ count) {
+                                       int32_t* __restrict__ idx, int32_t* __restrict__ count,
+                                       const int32_t* __restrict__ dev_n) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (dev_n) {
+    const int64_t dn = *dev_n;
+    nf = dn < nf ? dn : nf;
+  }
   if (f >= nf) return;
   // RMS residual sqrt(chi2 / (k - 4)) > 2 sigma  <=>  chi2 > 4 sigma^2 (k - 4)
   const float c = chi2[f];
@@ -303,14 +308,15 @@ __global__ void fallback_select_kernel(const float* __restrict__ chi2, int64_t n
 }  // namespace
 
 hipError_t launch_fallback_select(const float* chi2, int64_t nf, int k, float noise_floor,
-                                  int32_t* flags, int32_t* idx, int32_t* count, hipStream_t s) {
+                                  int32_t* flags, int32_t* idx, int32_t* count, hipStream_t s,
+                                  const int32_t* dev_n) {
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, count);
   const double dof = k > 4 ? (double)(k - 4) : 1.0;
   const float thr2 = (float)(4.0 * (double)noise_floor * (double)noise_floor * dof);
   const int64_t blocks = (nf + 255) / 256;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fallback_select_kernel, dim3((unsigned)blocks), dim3(256), 0, s, chi2, nf, k,
-                     thr2, flags, idx, count);
+                     thr2, flags, idx, count, dev_n);
   return hipGetLastError();
 }
 
@@ -326,13 +332,13 @@ int lm_chunk(int64_t nf) {
 
 hipError_t launch_lm(const float* y, const float* p0, int64_t nf, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
-                     int chunk) {
+                     int chunk, const int32_t* dev_n) {
   if (chunk <= 0) chunk = lm_chunk(nf);
   const int64_t waves = (nf + chunk - 1) / chunk;
   const int64_t blocks = (waves + 3) / 4;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   CG_DISPATCH_Q16(k, hipLaunchKernelGGL(lm_kernel<Q>, dim3((unsigned)blocks), dim3(256), 0, s, y,
-                                        p0, nullptr, nullptr, nf, k, max_iter, chunk, params,
+                                        p0, nullptr, dev_n, nf, k, max_iter, chunk, params,
                                         iters, status, chi2, -1));
   return hipGetLastError();
 }

@@ -25,7 +25,7 @@ cg_status make_mlp(const float* params, const float* mean, const float* stdv, fl
                    cg_mlp** out);
 void free_mlp(cg_mlp* m);
 hipError_t launch_mlp_infer(const cg_mlp* m, const float* y, int64_t nf, int k, float* p0,
-                            hipStream_t s);
+                            hipStream_t s, const int32_t* dev_n = nullptr);
 
 cg_status make_trainer(int32_t batch, const float* init, cg_mlp_trainer** out);
 void free_trainer(cg_mlp_trainer* t);

@@ -256,12 +256,17 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(
     const float* __restrict__ y, int64_t nf, int k, const uint16_t* __restrict__ w1,
     const float* __restrict__ b1, const uint16_t* __restrict__ w2, const float* __restrict__ b2,
     const uint16_t* __restrict__ w3, const float* __restrict__ b3, MlpScale sc,
-    float* __restrict__ p0) {
+    float* __restrict__ p0, const int32_t* __restrict__ dev_n) {
   __shared__ __attribute__((aligned(16))) uint16_t s_x[IB * HP];
   __shared__ __attribute__((aligned(16))) uint16_t s_h[IB * HP];
   __shared__ float s_out[IB * 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t f0 = (int64_t)blockIdx.x * IB;
+  if (dev_n) {
+    const int64_t dn = *dev_n;
+    nf = dn < nf ? dn : nf;
+  }
+  if (f0 >= nf) return;
   const int fr = lane & 15, kq = (lane >> 4) * 8;
 
   // input: resample to 220 points when k != 220, round to bf16, zero pad
@@ -429,11 +434,11 @@ cg_status make_mlp(const float* params, const float* mean, const float* stdv, fl
 }
 
 hipError_t launch_mlp_infer(const cg_mlp* m, const float* y, int64_t nf, int k, float* p0,
-                            hipStream_t s) {
+                            hipStream_t s, const int32_t* dev_n) {
   const int64_t blocks = (nf + IB - 1) / IB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)blocks), dim3(256), 0, s, y, nf, k, m->w1,
-                     m->b1, m->w2, m->b2, m->w3, m->b3, m->scale, p0);
+                     m->b1, m->w2, m->b2, m->w3, m->b3, m->scale, p0, dev_n);
   return hipGetLastError();
 }
 

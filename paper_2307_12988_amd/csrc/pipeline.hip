@@ -1,0 +1,557 @@
+// Multi-stream ring pipeline: many concurrent comb streams with their own frame
+// length, tooth count, reference and network, arriving as interleaved bursts.
+//
+// Paper, Data Capture and Processing: the digitiser fills a ring buffer, the
+// GPU works on batches asynchronously across many threads, batches may finish
+// out of order and are sorted back into a time-contiguous record; streaming
+// continues indefinitely only while data are consumed as fast as they are
+// produced, otherwise the buffer overflows and acquisition stops.
+//
+// Design
+// ------
+// * Device ring: every stream owns R slots of device memory, each holding one
+//   burst of up to `cap` frames, its normalised spectra, workspace and results.
+//   A producer acquires a free slot (CG_ERR_RING_FULL when none is free: the
+//   overflow is counted and the burst is not taken), writes the frames, and
+//   publishes (stream, slot, n, seq).  Published bursts form one global queue
+//   in publish order, interleaving the streams.
+// * Graphs: at creation each slot's whole processing chain (transform, start
+//   point, fit, fallback) is captured once into a hipGraph with the slot's
+//   fixed buffers; the burst size is read by the kernels from a device count
+//   in the slot, so one graph serves any burst up to `cap`.
+// * Dispatcher: one persistent host thread drains the queue in publish order:
+//   per burst it copies the count, launches the slot's graph on the stream's
+//   HIP stream, queues the copy of the results to pinned host memory and an
+//   event; it polls the events and records publish-to-results latency on the
+//   host clock.  Work of different streams overlaps on the GPU; within a
+//   stream bursts complete in order, so per-stream results come out in seq
+//   order (checked on read).
+// * Dry run (CG_PIPE_DRY_RUN): the same bookkeeping with no device work; a
+//   burst "completes" after dry_us_per_frame * n microseconds.  Used to test
+//   overflow handling and ordering on machines without a GPU.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "mlp.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+double now_s() {
+  return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+enum SlotState : int { FREE = 0, WRITING = 1, QUEUED = 2, RUNNING = 3, DONE = 4 };
+
+struct PipeSlot {
+  int16_t* frames = nullptr;
+  int32_t* n_dev = nullptr;
+  int32_t* n_host = nullptr;  // pinned
+  char* ws = nullptr;
+  float* y = nullptr;
+  float* p0 = nullptr;
+  float* chi2 = nullptr;
+  int32_t* fb_flags = nullptr;
+  int32_t* fb_idx = nullptr;
+  int32_t* fb_count = nullptr;
+  float* params = nullptr;
+  int32_t* status = nullptr;
+  int32_t* iters = nullptr;
+  float* h_params = nullptr;   // pinned
+  int32_t* h_status = nullptr;  // pinned
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  int state = FREE;
+  int64_t seq = 0;
+  int32_t n = 0;
+  double t_pub = 0.0, t_done = 0.0;
+};
+
+struct PipeStream {
+  cg_plan* plan = nullptr;
+  uint32_t flags = 0;
+  hipStream_t hs = nullptr;
+  std::vector<PipeSlot> slots;
+  int cursor = 0;
+  int64_t last_seq_read = -1;
+  std::deque<int> completed;  // slot indices in completion (= publish) order
+  int64_t bursts = 0, frames = 0;
+};
+
+}  // namespace
+
+struct cg_pipeline {
+  bool dry = false;
+  bool keep = false;
+  double dry_us = 0.0;
+  int device = 0;
+  int cap = 0;
+  std::vector<PipeStream> st;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::pair<int, int>> queue;
+  std::vector<std::pair<int, int>> running;
+  std::thread worker;
+  bool stop = false;
+  bool failed = false;
+  std::string fail_detail;
+  int64_t overflows = 0, bursts = 0, frames = 0;
+  double bytes = 0.0;
+  double t_first = -1.0, t_last = 0.0;
+  std::vector<float> lat_ms;
+};
+
+namespace cg {
+namespace {
+
+constexpr size_t kLatKeep = 1 << 20;
+
+size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
+  const cg_plan* p = ps.plan;
+  hipStream_t s = ps.hs;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = launch_fft_teeth(p, sl.frames, cap, nullptr, sl.y, s, sl.n_dev);
+  if ((ps.flags & CG_FIT_MASK) == CG_FIT_WARM_MLP) {
+    if (le == hipSuccess) le = launch_mlp_infer(p->mlp, sl.y, cap, p->k, sl.p0, s, sl.n_dev);
+    if (le == hipSuccess)
+      le = launch_lm(sl.y, sl.p0, cap, p->k, 2, sl.params, sl.iters, sl.status, sl.chi2, s,
+                     p->lm_chunk, sl.n_dev);
+    if (le == hipSuccess)
+      le = launch_fallback_select(sl.chi2, cap, p->k, p->mlp->noise_floor, sl.fb_flags, sl.fb_idx,
+                                  sl.fb_count, s, sl.n_dev);
+    if (le == hipSuccess)
+      le = launch_median_start(sl.y, cap, p->k, nullptr, sl.p0, s, sl.fb_flags, sl.n_dev);
+    if (le == hipSuccess)
+      le = launch_lm_indexed(sl.y, sl.p0, sl.fb_idx, sl.fb_count, cap, p->k, 20, sl.params,
+                             sl.iters, sl.status, sl.chi2, CG_FIT_FALLBACK, s);
+  } else {
+    if (le == hipSuccess)
+      le = launch_median_start(sl.y, cap, p->k, nullptr, sl.p0, s, nullptr, sl.n_dev);
+    if (le == hipSuccess)
+      le = launch_lm(sl.y, sl.p0, cap, p->k, 20, sl.params, sl.iters, sl.status, sl.chi2, s,
+                     p->lm_chunk, sl.n_dev);
+  }
+  e = hipStreamEndCapture(s, &sl.graph);
+  if (le != hipSuccess) return le;
+  if (e != hipSuccess) return e;
+  return hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0);
+}
+
+void free_slot(PipeSlot& sl) {
+  if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+  if (sl.graph) (void)hipGraphDestroy(sl.graph);
+  if (sl.done) (void)hipEventDestroy(sl.done);
+  if (sl.frames) (void)hipFree(sl.frames);
+  if (sl.ws) (void)hipFree(sl.ws);
+  if (sl.n_host) (void)hipHostFree(sl.n_host);
+  if (sl.h_params) (void)hipHostFree(sl.h_params);
+  if (sl.h_status) (void)hipHostFree(sl.h_status);
+}
+
+hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
+  const cg_plan* p = ps.plan;
+  hipError_t e = hipMalloc(&sl.frames, (size_t)cap * p->n * sizeof(int16_t));
+  if (e != hipSuccess) return e;
+  // one device block for the count, spectra, start points and results
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += a256(b);
+    return o;
+  };
+  const size_t o_n = take(sizeof(int32_t)), o_y = take((size_t)cap * p->k * 4),
+               o_p0 = take((size_t)cap * 16), o_c2 = take((size_t)cap * 4),
+               o_fl = take((size_t)cap * 4), o_ix = take((size_t)cap * 4), o_ct = take(4),
+               o_pr = take((size_t)cap * 16), o_st = take((size_t)cap * 4),
+               o_it = take((size_t)cap * 4);
+  if ((e = hipMalloc(&sl.ws, off)) != hipSuccess) return e;
+  sl.n_dev = reinterpret_cast<int32_t*>(sl.ws + o_n);
+  sl.y = reinterpret_cast<float*>(sl.ws + o_y);
+  sl.p0 = reinterpret_cast<float*>(sl.ws + o_p0);
+  sl.chi2 = reinterpret_cast<float*>(sl.ws + o_c2);
+  sl.fb_flags = reinterpret_cast<int32_t*>(sl.ws + o_fl);
+  sl.fb_idx = reinterpret_cast<int32_t*>(sl.ws + o_ix);
+  sl.fb_count = reinterpret_cast<int32_t*>(sl.ws + o_ct);
+  sl.params = reinterpret_cast<float*>(sl.ws + o_pr);
+  sl.status = reinterpret_cast<int32_t*>(sl.ws + o_st);
+  sl.iters = reinterpret_cast<int32_t*>(sl.ws + o_it);
+  if ((e = hipHostMalloc(&sl.n_host, sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&sl.h_params, (size_t)cap * 16)) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&sl.h_status, (size_t)cap * 4)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) return e;
+  return capture_slot(ps, sl, cap);
+}
+
+// launch one burst (dispatcher thread, no lock held)
+hipError_t launch_burst(cg_pipeline* P, int si, int li) {
+  PipeStream& ps = P->st[si];
+  PipeSlot& sl = ps.slots[li];
+  *sl.n_host = sl.n;
+  hipError_t e = hipMemcpyAsync(sl.n_dev, sl.n_host, sizeof(int32_t), hipMemcpyHostToDevice, ps.hs);
+  if (e == hipSuccess) e = hipGraphLaunch(sl.exec, ps.hs);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sl.h_params, sl.params, (size_t)sl.n * 16, hipMemcpyDeviceToHost, ps.hs);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sl.h_status, sl.status, (size_t)sl.n * 4, hipMemcpyDeviceToHost, ps.hs);
+  if (e == hipSuccess) e = hipEventRecord(sl.done, ps.hs);
+  return e;
+}
+
+void complete(cg_pipeline* P, int si, int li, double t) {
+  PipeStream& ps = P->st[si];
+  PipeSlot& sl = ps.slots[li];
+  sl.t_done = t;
+  ps.bursts += 1;
+  ps.frames += sl.n;
+  P->bursts += 1;
+  P->frames += sl.n;
+  P->bytes += (double)sl.n * (P->dry ? 0.0 : (double)ps.plan->n * 2.0);
+  P->t_last = t;
+  if (P->lat_ms.size() < kLatKeep) P->lat_ms.push_back((float)((t - sl.t_pub) * 1e3));
+  if (P->keep) {
+    sl.state = DONE;
+    ps.completed.push_back(li);
+  } else {
+    sl.state = FREE;
+  }
+}
+
+void dispatcher(cg_pipeline* P) {
+  if (!P->dry) (void)hipSetDevice(P->device);
+  std::vector<std::pair<int, int>> todo;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(P->mu);
+      if (P->queue.empty() && P->running.empty()) {
+        P->cv.notify_all();  // idle: wake drain()
+        P->cv.wait_for(lk, std::chrono::microseconds(200),
+                       [&] { return P->stop || !P->queue.empty(); });
+        if (P->stop && P->queue.empty() && P->running.empty()) return;
+      }
+      todo.assign(P->queue.begin(), P->queue.end());
+      P->queue.clear();
+      for (auto& q : todo) P->st[q.first].slots[q.second].state = RUNNING;
+    }
+    // launches, in publish order
+    for (auto& q : todo) {
+      if (!P->dry) {
+        hipError_t e = launch_burst(P, q.first, q.second);
+        if (e != hipSuccess) {
+          std::lock_guard<std::mutex> lk(P->mu);
+          P->failed = true;
+          P->fail_detail = std::string("pipeline launch: ") + hipGetErrorString(e);
+        }
+      }
+      std::lock_guard<std::mutex> lk(P->mu);
+      P->running.push_back(q);
+    }
+    todo.clear();
+    // completions
+    {
+      std::lock_guard<std::mutex> lk(P->mu);
+      const double t = now_s();
+      std::vector<std::pair<int, int>> still;
+      for (auto& q : P->running) {
+        PipeSlot& sl = P->st[q.first].slots[q.second];
+        bool finished;
+        if (P->dry) {
+          finished = t >= sl.t_pub + 1e-6 * P->dry_us * sl.n;
+        } else {
+          const hipError_t qe = hipEventQuery(sl.done);
+          finished = qe != hipErrorNotReady;
+          if (finished && qe != hipSuccess) {
+            P->failed = true;
+            P->fail_detail = std::string("pipeline burst: ") + hipGetErrorString(qe);
+          }
+        }
+        if (finished)
+          complete(P, q.first, q.second, t);
+        else
+          still.push_back(q);
+      }
+      P->running.swap(still);
+    }
+    if (!P->running.empty()) std::this_thread::yield();
+  }
+}
+
+}  // namespace
+}  // namespace cg
+
+using cg::hip_fail;
+
+extern "C" {
+
+cg_status cg_pipeline_create(int32_t n_streams, cg_plan* const* plans, const uint32_t* fit_flags,
+                             int32_t slots_per_stream, int32_t max_burst_frames, uint32_t options,
+                             double dry_us_per_frame, cg_pipeline** out) {
+  if (!out) return CG_ERR_NULL;
+  *out = nullptr;
+  if (n_streams < 1 || n_streams > CG_PIPE_MAX_STREAMS || slots_per_stream < 1 ||
+      slots_per_stream > 64 || max_burst_frames < 1 || max_burst_frames > (1 << 20))
+    return CG_ERR_INVALID_ARG;
+  if ((options & ~(CG_PIPE_KEEP_RESULTS | CG_PIPE_DRY_RUN)) != 0u) return CG_ERR_INVALID_ARG;
+  const bool dry = (options & CG_PIPE_DRY_RUN) != 0u;
+  if (dry && !(dry_us_per_frame >= 0.0)) return CG_ERR_INVALID_ARG;
+  if (!dry) {
+    if (!plans || !fit_flags) return CG_ERR_NULL;
+    for (int i = 0; i < n_streams; ++i) {
+      if (!plans[i]) return CG_ERR_NULL;
+      const uint32_t f = fit_flags[i];
+      if (f != CG_FIT_COLD && f != CG_FIT_WARM_MLP) return CG_ERR_INVALID_ARG;
+      if (f == CG_FIT_WARM_MLP && !plans[i]->mlp) return CG_ERR_STATE;
+    }
+  }
+  cg_pipeline* P = new (std::nothrow) cg_pipeline();
+  if (!P) return CG_ERR_OOM;
+  P->dry = dry;
+  P->keep = (options & CG_PIPE_KEEP_RESULTS) != 0u;
+  P->dry_us = dry_us_per_frame;
+  P->cap = max_burst_frames;
+  P->st.resize(n_streams);
+  hipError_t e = hipSuccess;
+  if (!dry) e = hipGetDevice(&P->device);
+  for (int i = 0; i < n_streams && e == hipSuccess; ++i) {
+    PipeStream& ps = P->st[i];
+    ps.slots.resize(slots_per_stream);
+    if (dry) continue;
+    ps.plan = plans[i];
+    ps.flags = fit_flags[i];
+    e = hipStreamCreateWithFlags(&ps.hs, hipStreamNonBlocking);
+    for (int j = 0; j < slots_per_stream && e == hipSuccess; ++j)
+      e = cg::alloc_slot(ps, ps.slots[j], max_burst_frames);
+  }
+  if (e != hipSuccess) {
+    const cg_status st = hip_fail(e, "cg_pipeline_create");
+    cg_pipeline_destroy(P);
+    return st;
+  }
+  P->worker = std::thread(cg::dispatcher, P);
+  *out = P;
+  return CG_OK;
+}
+
+cg_status cg_pipeline_destroy(cg_pipeline* P) {
+  if (!P) return CG_OK;
+  if (P->worker.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(P->mu);
+      P->stop = true;
+    }
+    P->cv.notify_all();
+    P->worker.join();
+  }
+  if (!P->dry) {
+    (void)hipDeviceSynchronize();
+    for (auto& ps : P->st) {
+      for (auto& sl : ps.slots) cg::free_slot(sl);
+      if (ps.hs) (void)hipStreamDestroy(ps.hs);
+    }
+  }
+  delete P;
+  return CG_OK;
+}
+
+cg_status cg_pipeline_acquire(cg_pipeline* P, int32_t stream, int32_t* slot, int16_t** frames) {
+  if (!P || !slot) return CG_ERR_NULL;
+  if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(P->mu);
+  if (P->failed) {
+    cg::set_detail(P->fail_detail);
+    return CG_ERR_HIP;
+  }
+  PipeStream& ps = P->st[stream];
+  const int r = (int)ps.slots.size();
+  for (int t = 0; t < r; ++t) {
+    const int j = (ps.cursor + t) % r;
+    if (ps.slots[j].state == FREE) {
+      ps.slots[j].state = WRITING;
+      ps.cursor = (j + 1) % r;
+      *slot = j;
+      if (frames) *frames = ps.slots[j].frames;
+      return CG_OK;
+    }
+  }
+  P->overflows += 1;
+  cg::set_detail("ring full: every slot of this stream is queued, running or unread");
+  return CG_ERR_RING_FULL;
+}
+
+cg_status cg_pipeline_publish(cg_pipeline* P, int32_t stream, int32_t slot, int32_t n_frames,
+                              int64_t seq) {
+  if (!P) return CG_ERR_NULL;
+  if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
+  if (n_frames < 1 || n_frames > P->cap) return CG_ERR_INVALID_ARG;
+  {
+    std::lock_guard<std::mutex> lk(P->mu);
+    PipeStream& ps = P->st[stream];
+    if (slot < 0 || slot >= (int32_t)ps.slots.size() || ps.slots[slot].state != WRITING)
+      return CG_ERR_INVALID_ARG;
+    PipeSlot& sl = ps.slots[slot];
+    sl.n = n_frames;
+    sl.seq = seq;
+    sl.t_pub = now_s();
+    if (P->t_first < 0) P->t_first = sl.t_pub;
+    sl.state = QUEUED;
+    P->queue.emplace_back(stream, slot);
+  }
+  P->cv.notify_all();
+  return CG_OK;
+}
+
+cg_status cg_pipeline_put(cg_pipeline* P, int32_t stream, const int16_t* src, int32_t n_frames,
+                          int64_t seq) {
+  if (!P || !src) return CG_ERR_NULL;
+  if (P->dry) return CG_ERR_STATE;
+  if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
+  if (n_frames < 1 || n_frames > P->cap) return CG_ERR_INVALID_ARG;
+  int32_t slot = -1;
+  int16_t* dst = nullptr;
+  cg_status st = cg_pipeline_acquire(P, stream, &slot, &dst);
+  if (st != CG_OK) return st;
+  PipeStream& ps = P->st[stream];
+  // queued on the stream's own HIP stream, so it precedes the burst's graph
+  const hipError_t e = hipMemcpyAsync(dst, src, (size_t)n_frames * ps.plan->n * sizeof(int16_t),
+                                      hipMemcpyDefault, ps.hs);
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> lk(P->mu);
+    ps.slots[slot].state = FREE;
+    return hip_fail(e, "cg_pipeline_put copy");
+  }
+  return cg_pipeline_publish(P, stream, slot, n_frames, seq);
+}
+
+cg_status cg_pipeline_read(cg_pipeline* P, int32_t stream, float* params, int32_t* status,
+                           int32_t capacity, int32_t* n_frames, int64_t* seq) {
+  if (!P || !n_frames) return CG_ERR_NULL;
+  if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(P->mu);
+  PipeStream& ps = P->st[stream];
+  if (ps.completed.empty()) {
+    *n_frames = 0;
+    return CG_ERR_STATE;
+  }
+  const int j = ps.completed.front();
+  PipeSlot& sl = ps.slots[j];
+  if (sl.n > capacity) return CG_ERR_INVALID_ARG;
+  ps.completed.pop_front();
+  if (sl.seq <= ps.last_seq_read) {
+    cg::set_detail("results out of order");
+    sl.state = FREE;
+    return CG_ERR_STATE;
+  }
+  ps.last_seq_read = sl.seq;
+  *n_frames = sl.n;
+  if (seq) *seq = sl.seq;
+  if (!P->dry) {
+    if (params) std::memcpy(params, sl.h_params, (size_t)sl.n * 16);
+    if (status) std::memcpy(status, sl.h_status, (size_t)sl.n * 4);
+  }
+  sl.state = FREE;
+  return CG_OK;
+}
+
+cg_status cg_pipeline_drain(cg_pipeline* P, int32_t timeout_ms) {
+  if (!P) return CG_ERR_NULL;
+  std::unique_lock<std::mutex> lk(P->mu);
+  const bool ok = P->cv.wait_for(lk, std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms),
+                                 [&] { return P->queue.empty() && P->running.empty(); });
+  if (P->failed) {
+    cg::set_detail(P->fail_detail);
+    return CG_ERR_HIP;
+  }
+  if (!ok) {
+    cg::set_detail("drain timed out");
+    return CG_ERR_STATE;
+  }
+  return CG_OK;
+}
+
+cg_status cg_pipeline_stats(cg_pipeline* P, double* out, int32_t n_out) {
+  if (!P || !out) return CG_ERR_NULL;
+  if (n_out < CG_PIPE_NSTATS) return CG_ERR_INVALID_ARG;
+  std::vector<float> lat;
+  std::lock_guard<std::mutex> lk(P->mu);
+  lat = P->lat_ms;
+  auto pct = [&](double q) -> double {
+    if (lat.empty()) return 0.0;
+    const size_t i = std::min(lat.size() - 1, (size_t)(q * (double)(lat.size() - 1) + 0.5));
+    std::nth_element(lat.begin(), lat.begin() + i, lat.end());
+    return lat[i];
+  };
+  const double span = P->t_first >= 0 ? P->t_last - P->t_first : 0.0;
+  out[0] = (double)P->bursts;
+  out[1] = (double)P->frames;
+  out[2] = P->bytes;
+  out[3] = (double)P->overflows;
+  out[4] = span;
+  out[5] = pct(0.5);
+  out[6] = pct(0.99);
+  out[7] = lat.empty() ? 0.0 : (double)*std::max_element(lat.begin(), lat.end());
+  out[8] = span > 0 ? P->bytes / span : 0.0;
+  out[9] = span > 0 ? (double)P->frames / span : 0.0;
+  return CG_OK;
+}
+
+cg_status cg_autotune(cg_plan* p, const int16_t* frames, int64_t nf, uint32_t flags,
+                      void* workspace, size_t workspace_bytes, int32_t* chosen, float* best_ms) {
+  if (!p || !frames || !chosen) return CG_ERR_NULL;
+  if (nf < 1) return CG_ERR_INVALID_ARG;
+  const int cands[] = {4, 8, 16, 32, 64};
+  float* params = nullptr;
+  hipError_t e = hipMalloc(&params, (size_t)nf * 16);
+  if (e != hipSuccess) return hip_fail(e, "autotune alloc");
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  const int32_t saved = p->lm_chunk;
+  float best = 1e30f;
+  int32_t pick = 0;
+  cg_status st = CG_OK;
+  for (int c : cands) {
+    p->lm_chunk = c;
+    // one untimed pass, then three timed ones
+    for (int r = 0; r < 4 && st == CG_OK; ++r) {
+      if (r == 1) (void)hipEventRecord(a, nullptr);
+      st = cg_process_batch_ex(p, frames, nf, params, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               flags, workspace, workspace_bytes, nullptr);
+    }
+    if (st != CG_OK) break;
+    (void)hipEventRecord(b, nullptr);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    ms /= 3.f;
+    if (ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipFree(params);
+  if (st != CG_OK) {
+    p->lm_chunk = saved;
+    return st;
+  }
+  p->lm_chunk = pick;
+  *chosen = pick;
+  if (best_ms) *best_ms = best;
+  return CG_OK;
+}
+
+}  // extern "C"

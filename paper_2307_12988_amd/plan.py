@@ -231,6 +231,17 @@ class Plan:
         _lib.check(st, "cg_mlp_infer")
         return out
 
+    def autotune(self, frames, flags: int = 0):
+        """Pick the fastest fit-kernel launch shape for these frames; returns
+        (spectra per wavefront, ms per batch)."""
+        nf, fp = self._frames(frames)
+        chosen = ctypes.c_int32()
+        best = ctypes.c_float()
+        st = self._lib.cg_autotune(self._h, fp, nf, int(flags), None, 0, ctypes.byref(chosen),
+                                   ctypes.byref(best))
+        _lib.check(st, "cg_autotune")
+        return chosen.value, best.value
+
     def median_filter(self, y, out=None):
         nf = int(y.shape[0])
         yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")
@@ -334,3 +345,112 @@ class Trainer:
         _lib.check(self._lib.cg_mlp_get_params(self._h, out.ctypes.data_as(_lib._pf32)),
                    "cg_mlp_get_params")
         return out
+
+
+PIPE_KEEP_RESULTS = 0x1
+PIPE_DRY_RUN = 0x2
+STATS_FIELDS = ("bursts", "frames", "bytes", "overflows", "seconds", "lat_p50_ms", "lat_p99_ms",
+                "lat_max_ms", "bytes_per_s", "frames_per_s")
+
+
+class RingFull(_lib.CombGpuError):
+    pass
+
+
+class Pipeline:
+    """Multi-stream ring pipeline (see cg_pipeline_create).  `plans` and
+    `fit_flags` per stream; in dry-run mode pass `n_streams` instead."""
+
+    def __init__(self, plans=None, fit_flags=None, slots_per_stream=4, max_burst_frames=4096,
+                 keep_results=False, dry_run_us_per_frame=None, n_streams=None):
+        self._lib = _lib.load()
+        opts = PIPE_KEEP_RESULTS if keep_results else 0
+        if dry_run_us_per_frame is not None:
+            opts |= PIPE_DRY_RUN
+            ns = int(n_streams)
+            arr_p = arr_f = None
+            dry = float(dry_run_us_per_frame)
+        else:
+            ns = len(plans)
+            arr_p = (ctypes.c_void_p * ns)(*[p._h.value for p in plans])
+            arr_f = (ctypes.c_uint32 * ns)(*[int(f) for f in fit_flags])
+            dry = 0.0
+        self._plans = plans  # keep alive
+        h = ctypes.c_void_p()
+        st = self._lib.cg_pipeline_create(ns, arr_p, arr_f, int(slots_per_stream),
+                                          int(max_burst_frames), opts, dry, ctypes.byref(h))
+        _lib.check(st, "cg_pipeline_create")
+        self._h = h
+        self.n_streams = ns
+        self.max_burst = int(max_burst_frames)
+        self.slots = int(slots_per_stream)
+        # sources of queued copies stay referenced until their slot has been
+        # recycled (bursts of one stream complete in order, so R puts later)
+        self._held = [[] for _ in range(ns)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.cg_pipeline_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def acquire(self, stream: int):
+        """Returns (slot, device pointer of the slot's frame buffer) or raises RingFull."""
+        slot = ctypes.c_int32()
+        ptr = ctypes.c_void_p()
+        st = self._lib.cg_pipeline_acquire(self._h, int(stream), ctypes.byref(slot),
+                                           ctypes.byref(ptr))
+        if st == -9:
+            raise RingFull(st, "cg_pipeline_acquire")
+        _lib.check(st, "cg_pipeline_acquire")
+        return slot.value, ptr.value
+
+    def publish(self, stream: int, slot: int, n_frames: int, seq: int):
+        _lib.check(self._lib.cg_pipeline_publish(self._h, int(stream), int(slot), int(n_frames),
+                                                 int(seq)), "cg_pipeline_publish")
+
+    def put(self, stream: int, frames, seq: int):
+        """Copy a burst (torch int16 tensor on the GPU or pinned CPU tensor,
+        [n, frame_len], contiguous) into a free slot and publish it.  Raises
+        RingFull when the stream has no free slot."""
+        if not isinstance(frames, torch.Tensor) or frames.dtype != torch.int16 or \
+                frames.dim() != 2 or not frames.is_contiguous():
+            raise ValueError("frames must be a contiguous int16 torch tensor [n, frame_len]")
+        st = self._lib.cg_pipeline_put(self._h, int(stream), ctypes.c_void_p(frames.data_ptr()),
+                                       int(frames.shape[0]), int(seq))
+        if st == -9:
+            raise RingFull(st, "cg_pipeline_put")
+        _lib.check(st, "cg_pipeline_put")
+        held = self._held[int(stream)]
+        held.append(frames)
+        if len(held) > self.slots:
+            held.pop(0)
+
+    def read(self, stream: int):
+        """Oldest completed burst of `stream`: (seq, params [n,4], status [n]) or None."""
+        params = np.empty((self.max_burst, 4), dtype=np.float32)
+        status = np.empty(self.max_burst, dtype=np.int32)
+        n = ctypes.c_int32()
+        seq = ctypes.c_int64()
+        st = self._lib.cg_pipeline_read(self._h, int(stream), params.ctypes.data_as(_lib._pf32),
+                                        status.ctypes.data_as(_lib._pi32), self.max_burst,
+                                        ctypes.byref(n), ctypes.byref(seq))
+        if st == -8 and n.value == 0:
+            return None
+        _lib.check(st, "cg_pipeline_read")
+        return seq.value, params[:n.value].copy(), status[:n.value].copy()
+
+    def drain(self, timeout_ms: int = 60000):
+        _lib.check(self._lib.cg_pipeline_drain(self._h, int(timeout_ms)), "cg_pipeline_drain")
+        self._held = [[] for _ in range(self.n_streams)]
+
+    def stats(self):
+        out = (ctypes.c_double * len(STATS_FIELDS))()
+        _lib.check(self._lib.cg_pipeline_stats(self._h, out, len(STATS_FIELDS)),
+                   "cg_pipeline_stats")
+        return dict(zip(STATS_FIELDS, list(out)))

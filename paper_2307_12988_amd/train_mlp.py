@@ -4,11 +4,12 @@
         [--out paper_2307_12988_amd/data/warmstart_learned.npz]
 
 1. Synthetic frames of the warm-start training distribution (centre
-   mid +- 40 teeth, FWHM U[3,20], depth U[0.1,0.9], SNR U[15,50] dB, linear
-   baseline tilt +-5 %, 2048 samples, 220 teeth), seed 3; hold-out seed 4.
+   mid +- 40 teeth, FWHM 3..20, depth 0.1..0.9, SNR 15..50 dB, linear baseline
+   tilt +-5 %, each drifting continuously; 2048 samples, 220 teeth), seed 3;
+   hold-out seed 4.
 2. The GPU path turns them into normalised spectra and cold-start
-   Levenberg-Marquardt fits; converged fits are the labels (the others get
-   weight 0).
+   Levenberg-Marquardt fits; converged fits of a dip inside the comb are the
+   labels (the others get weight 0).
 3. Calibration constants, computed on the host from those GPU outputs: the
    per-output mean and standard deviation of the labels, and the noise floor
    (median RMS residual sqrt(chi2 / (K - 4)) of the converged fits).
@@ -84,11 +85,14 @@ def label_set(plan, spec, n_samples, seed, dev, workers=8, log=print):
 
 
 def calibration(params, status, chi2, k):
-    """Label mean/std over converged fits and the noise floor (host)."""
+    """Label mean/std over kept fits and the noise floor (host).  Kept: the
+    cold-start fit converged to a dip inside the comb (0 <= c <= K-1,
+    0 < w < K, 0 < d <= 1.5)."""
     p = params.cpu().numpy().astype(np.float64)
     st = status.cpu().numpy()
     c2 = chi2.cpu().numpy().astype(np.float64)
-    ok = st == 0
+    ok = (st == 0) & (p[:, 0] >= 0) & (p[:, 0] <= k - 1) & (p[:, 1] > 0) & (p[:, 1] < k) & \
+        (p[:, 2] > 0) & (p[:, 2] <= 1.5) & np.all(np.isfinite(p), axis=1)
     mean = p[ok].mean(axis=0)
     std = p[ok].std(axis=0)
     noise = float(np.median(np.sqrt(np.maximum(c2[ok], 0.0) / (k - 4))))

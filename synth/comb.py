@@ -19,7 +19,8 @@ Synthesis recipe, one frame of N samples at sample rate fs:
   (unit teeth, no dip).
 
 The centre moves as c(t) = c_mid + amp * sin(2 pi f_mech t) with t the start
-time of the frame, or is drawn uniformly per frame (learned warm-start data).
+time of the frame, or (learned warm-start data) every parameter sweeps its
+range along a slow sinusoid; a per-frame uniform draw is also available.
 Per-frame width, depth, SNR and tilt are drawn uniformly from the ranges in the
 spec.  Random numbers come from numpy's PCG64 seeded by (seed, batch index),
 so any batch of any stream is reproducible on its own.
@@ -76,7 +77,7 @@ class StreamSpec:
     fs: float
     bins: np.ndarray
     f_mech: float = _F_MECH_HZ
-    centre_mode: str = "sine"          # "sine" or "uniform"
+    centre_mode: str = "sine"          # "sine", "uniform" or "drift"
     centre_amp: float = 10.0           # sine amplitude, teeth
     centre_halfrange: float = 40.0     # uniform mode: mid +- this
     centre_mid: Optional[float] = None  # default (K-1)/2
@@ -175,6 +176,19 @@ def make_batch(spec: StreamSpec, n_frames: int, seed: int, batch_index: int = 0,
     elif spec.centre_mode == "uniform":
         centre = _uniform(rng, (spec.mid - spec.centre_halfrange, spec.mid + spec.centre_halfrange),
                           n_frames)
+    elif spec.centre_mode == "drift":
+        # every parameter sweeps its range along a slow sinusoid (random rate and
+        # phase per batch), so consecutive frames see a continuously moving dip
+        def sweep(lo, hi, f_lo, f_hi):
+            f = rng.uniform(f_lo, f_hi)
+            ph = rng.uniform(0.0, 2.0 * np.pi)
+            return lo + (hi - lo) * (0.5 + 0.5 * np.sin(2.0 * np.pi * f * t_start + ph))
+        centre = sweep(spec.mid - spec.centre_halfrange, spec.mid + spec.centre_halfrange,
+                       100.0, 800.0)
+        width = sweep(spec.width[0], spec.width[1], 10.0, 200.0)
+        depth = sweep(spec.depth[0], spec.depth[1], 10.0, 200.0)
+        snr = sweep(spec.snr_db[0], spec.snr_db[1], 10.0, 200.0)
+        tilt = sweep(spec.tilt[0], spec.tilt[1], 10.0, 200.0)
     else:
         raise ValueError(spec.centre_mode)
     baseline = np.full(n_frames, float(spec.baseline))
@@ -249,10 +263,12 @@ def spec_precision() -> StreamSpec:
 
 
 def spec_learned() -> StreamSpec:
-    """Warm-start training distribution: centre mid+-40, FWHM U[3,20], depth
-    U[0.1,0.9], SNR U[15,50] dB, linear baseline tilt U[-5%,+5%]."""
+    """Warm-start training distribution: centre mid+-40, FWHM 3..20, depth
+    0.1..0.9, SNR 15..50 dB, linear baseline tilt +-5%, each swept along a
+    slow sinusoid (centre at 100-800 Hz, the others at 10-200 Hz) so the dip
+    moves continuously from frame to frame."""
     return StreamSpec(name="learned", n=2048, fs=1.1e9, bins=tooth_bins_interleaved(2048, 220),
-                      centre_mode="uniform", centre_halfrange=40.0, width=(3.0, 20.0),
+                      centre_mode="drift", centre_halfrange=40.0, width=(3.0, 20.0),
                       depth=(0.1, 0.9), snr_db=(15.0, 50.0), tilt=(-0.05, 0.05))
 
 
