@@ -75,6 +75,21 @@ hipStream_t pick(const cg_plan*, void* s) { return reinterpret_cast<hipStream_t>
 
 bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
 
+}  // namespace
+
+// reference and 0.5/reference (the FFT epilogue multiplies 2|X| by it)
+hipError_t upload_reference(cg_plan* p, const float* ref) {
+  std::vector<float> half_inv(p->k);
+  for (int i = 0; i < p->k; ++i) half_inv[i] = (float)(0.5 / (double)ref[i]);
+  hipError_t e = hipMemcpy(p->d_ref, ref, sizeof(float) * p->k, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_half_inv_ref, half_inv.data(), sizeof(float) * p->k,
+                  hipMemcpyHostToDevice);
+  return e;
+}
+
+namespace {
+
 // Grow the plan-owned workspace to at least `bytes`.
 cg_status ensure_ws(cg_plan* p, size_t bytes) {
   if (bytes <= p->ws_bytes) return CG_OK;
@@ -94,6 +109,7 @@ void free_plan(cg_plan* p) {
   (void)hipDeviceSynchronize();
   if (p->d_bins) (void)hipFree(p->d_bins);
   if (p->d_ref) (void)hipFree(p->d_ref);
+  if (p->d_half_inv_ref) (void)hipFree(p->d_half_inv_ref);
   if (p->d_tw) (void)hipFree(p->d_tw);
   if (p->ws) (void)hipFree(p->ws);
   for (auto* b : p->d_mfma_bf)
@@ -177,11 +193,11 @@ cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins
   CG_TRY(hipGetDevice(&p->device), "hipGetDevice");
   CG_TRY(hipMalloc(&p->d_bins, sizeof(int32_t) * n_teeth), "hipMalloc bins");
   CG_TRY(hipMalloc(&p->d_ref, sizeof(float) * n_teeth), "hipMalloc ref");
+  CG_TRY(hipMalloc(&p->d_half_inv_ref, sizeof(float) * n_teeth), "hipMalloc inverse ref");
   CG_TRY(hipMalloc(&p->d_tw, sizeof(float2) * frame_len), "hipMalloc twiddles");
   CG_TRY(hipMemcpy(p->d_bins, tooth_bins, sizeof(int32_t) * n_teeth, hipMemcpyHostToDevice),
          "copy bins");
-  CG_TRY(hipMemcpy(p->d_ref, ref_spectrum, sizeof(float) * n_teeth, hipMemcpyHostToDevice),
-         "copy ref");
+  CG_TRY(cg::upload_reference(p, ref_spectrum), "copy ref");
   CG_TRY(hipMemcpy(p->d_tw, tw.data(), sizeof(float2) * frame_len, hipMemcpyHostToDevice),
          "copy twiddles");
 #undef CG_TRY
@@ -199,7 +215,7 @@ cg_status cg_set_reference(cg_plan* p, const float* ref) {
   cg_status st = cg::check_ref(ref, p->k);
   if (st != CG_OK) return st;
   hipError_t e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMemcpy(p->d_ref, ref, sizeof(float) * p->k, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = cg::upload_reference(p, ref);
   if (e != hipSuccess) return hip_fail(e, "cg_set_reference");
   p->h_ref.assign(ref, ref + p->k);
   return CG_OK;

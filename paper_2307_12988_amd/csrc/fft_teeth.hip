@@ -137,7 +137,7 @@ struct FftShape {
 template <int LOGM>
 __global__ __launch_bounds__(256) void fft_teeth_kernel(
     const int32_t* __restrict__ frames, int64_t n_frames, const int32_t* __restrict__ bins,
-    const float* __restrict__ ref, const c32* __restrict__ tw, int k_teeth,
+    const float* __restrict__ half_inv_ref, const c32* __restrict__ tw, int k_teeth,
     float* __restrict__ out_mag, float* __restrict__ out_y, const int32_t* __restrict__ dev_n) {
   using S = FftShape<LOGM>;
   constexpr int M = S::M, T = S::T, FPB = S::FPB, PM = S::PM, R3 = S::R3;
@@ -157,44 +157,52 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
   float* re = s_re + fl * PM;
   float* im = s_im + fl * PM;
 
+  // Padded LDS index padx(i) = i + i/16.  Each pass touches i = base + c*r
+  // with c a multiple of 16, so padx(base + c r) = padx(base) + (c + c/16) r:
+  // a per-thread base plus compile-time offsets.
   c32 v[16];
   // ---- pass 1: radix 16, Ns = 1, inputs straight from HBM ----
   {
-    const int32_t* src = frames + frame * M;
+    const int32_t* src = frames + frame * M + j;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      int32_t w = live ? __builtin_nontemporal_load(src + j + r * T) : 0;
+      int32_t w = live ? __builtin_nontemporal_load(src + r * T) : 0;
       v[r].x = (float)(int16_t)(w & 0xffff);
       v[r].y = (float)(w >> 16);
     }
     dft16(v);
+    float* wr = re + 17 * j;  // padx(16 j + r) = 17 j + r
+    float* wi = im + 17 * j;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int o = padx(16 * j + r);
-      re[o] = v[r].x;
-      im[o] = v[r].y;
+      wr[r] = v[r].x;
+      wi[r] = v[r].y;
     }
   }
   __syncthreads();
   // ---- pass 2: radix 16, Ns = 16 ----
   {
+    constexpr int S2 = T + T / 16;
+    const float* rr = re + j + (j >> 4);
+    const float* ri = im + j + (j >> 4);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int o = padx(j + r * T);
-      v[r].x = re[o];
-      v[r].y = im[o];
+      v[r].x = rr[r * S2];
+      v[r].y = ri[r * S2];
     }
     __syncthreads();
     const int jm = j & 15;
+    const int e2 = jm * (N / 256);  // pass-2 twiddle W_256^(jm r) = W_N^(e2 r)
 #pragma unroll
-    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw[(jm * r) * (N / 256)]);
+    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw[e2 * r]);
     dft16(v);
     const int base = (j >> 4) * 256 + jm;
+    float* wr = re + base + (base >> 4);
+    float* wi = im + base + (base >> 4);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int o = padx(base + 16 * r);
-      re[o] = v[r].x;
-      im[o] = v[r].y;
+      wr[17 * r] = v[r].x;
+      wi[17 * r] = v[r].y;
     }
   }
   __syncthreads();
@@ -204,11 +212,12 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int jp = j + T * q;
+      const float* rr = re + jp + (jp >> 4);
+      const float* ri = im + jp + (jp >> 4);
 #pragma unroll
       for (int r = 0; r < R3; ++r) {
-        const int o = padx(jp + 256 * r);
-        v[q * R3 + r].x = re[o];
-        v[q * R3 + r].y = im[o];
+        v[q * R3 + r].x = rr[272 * r];
+        v[q * R3 + r].y = ri[272 * r];
       }
     }
     __syncthreads();
@@ -218,11 +227,12 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 #pragma unroll
       for (int r = 1; r < R3; ++r) v[q * R3 + r] = cmul(v[q * R3 + r], tw[2 * jp * r]);
       dft_r<R3>(v + q * R3);
+      float* wr = re + jp + (jp >> 4);
+      float* wi = im + jp + (jp >> 4);
 #pragma unroll
       for (int r = 0; r < R3; ++r) {
-        const int o = padx(jp + 256 * r);
-        re[o] = v[q * R3 + r].x;
-        im[o] = v[q * R3 + r].y;
+        wr[272 * r] = v[q * R3 + r].x;
+        wi[272 * r] = v[q * R3 + r].y;
       }
     }
     __syncthreads();
@@ -238,10 +248,10 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
     const c32 s = cadd(a, b);
     const c32 o = mul_mi(csub(a, b));
     const c32 x = cadd(s, cmul(tw[kb], o));
-    const float mag = 0.5f * sqrtf(x.x * x.x + x.y * x.y);
+    const float r2 = __builtin_amdgcn_sqrtf(x.x * x.x + x.y * x.y);  // 2 |X[k]|
     const int64_t idx = frame * k_teeth + i;
-    if (out_mag) out_mag[idx] = mag;
-    if (out_y) out_y[idx] = mag / ref[i];
+    if (out_mag) out_mag[idx] = 0.5f * r2;
+    if (out_y) out_y[idx] = r2 * half_inv_ref[i];
   }
 }
 
@@ -252,7 +262,7 @@ hipError_t launch_t(const cg_plan* p, const int16_t* frames, int64_t nf, float* 
   const int64_t blocks = (nf + S::FPB - 1) / S::FPB;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fft_teeth_kernel<LOGM>, dim3((unsigned)blocks), dim3(256), 0, s,
-                     reinterpret_cast<const int32_t*>(frames), nf, p->d_bins, p->d_ref,
+                     reinterpret_cast<const int32_t*>(frames), nf, p->d_bins, p->d_half_inv_ref,
                      reinterpret_cast<const c32*>(p->d_tw), p->k, out_mag, out_y, dev_n);
   return hipGetLastError();
 }

@@ -21,6 +21,7 @@ struct cg_plan {
   int device = 0;
   int32_t* d_bins = nullptr;   // [k] tooth bins, optical order
   float* d_ref = nullptr;      // [k] reference amplitudes
+  float* d_half_inv_ref = nullptr;  // [k] 0.5 / reference (FFT epilogue)
   float2* d_tw = nullptr;      // [n] W_n^e = (cos 2 pi e/n, -sin 2 pi e/n), e = 0..n-1
   std::vector<int32_t> h_bins;
   std::vector<float> h_ref;
@@ -37,6 +38,9 @@ struct cg_plan {
 namespace cg {
 
 constexpr int kWaveSize = 64;
+
+// Copy a reference spectrum (host, k values) and its 0.5/ref table to the plan.
+hipError_t upload_reference(cg_plan* p, const float* ref);
 
 // Record a HIP failure as the thread's error detail and map it to a status.
 cg_status hip_fail(hipError_t e, const char* where);

@@ -156,7 +156,7 @@ __device__ __forceinline__ void load_spectrum(const float* __restrict__ y, int64
 }
 
 template <int Q>
-__global__ __launch_bounds__(256) void lm_kernel(const float* __restrict__ y,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lm_kernel(const float* __restrict__ y,
                                                  const float* __restrict__ p0,
                                                  const int32_t* __restrict__ idx,
                                                  const int32_t* __restrict__ count, int64_t nf,

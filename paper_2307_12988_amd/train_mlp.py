@@ -1,6 +1,6 @@
 """Train the learned warm start on spectra and fits the method itself generates.
 
-    python -m paper_2307_12988_amd.train_mlp [--samples 1048576] [--epochs 12]
+    python -m paper_2307_12988_amd.train_mlp [--samples 1048576] [--epochs 20]
         [--out paper_2307_12988_amd/data/warmstart_learned.npz]
 
 1. Synthetic frames of the warm-start training distribution (centre
@@ -8,14 +8,16 @@
    tilt +-5 %, each drifting continuously; 2048 samples, 220 teeth), seed 3;
    hold-out seed 4.
 2. The GPU path turns them into normalised spectra and cold-start
-   Levenberg-Marquardt fits; converged fits of a dip inside the comb are the
-   labels (the others get weight 0).
+   Levenberg-Marquardt fits; converged fits of a dip inside the comb
+   (0 <= c <= K-1, 1 < w < K/4, 0.02 < d <= 1.2) are the labels (the others get
+   weight 0).
 3. Calibration constants, computed on the host from those GPU outputs: the
    per-output mean and standard deviation of the labels, and the noise floor
    (median RMS residual sqrt(chi2 / (K - 4)) of the converged fits).
-4. Adam (lr 1e-3, betas 0.9/0.999, batch 1024) on the weighted MSE of the
-   standardised labels, He-normal initial weights and per-epoch shuffles drawn
-   from numpy's PCG64 with fixed seeds and passed to the kernels.
+4. Adam (betas 0.9/0.999, batch 1024, learning rate 1e-3 decayed along a
+   cosine to 1e-5 over the run) on the weighted MSE of the standardised
+   labels, He-normal initial weights and per-epoch shuffles drawn from numpy's
+   PCG64 with fixed seeds and passed to the kernels.
 5. Hold-out report: warm start (network + 2-iteration polish + fallback)
    against the cold start on the same frames.
 """
@@ -87,19 +89,20 @@ def label_set(plan, spec, n_samples, seed, dev, workers=8, log=print):
 def calibration(params, status, chi2, k):
     """Label mean/std over kept fits and the noise floor (host).  Kept: the
     cold-start fit converged to a dip inside the comb (0 <= c <= K-1,
-    0 < w < K, 0 < d <= 1.5)."""
+    1 < w < K/4, 0.02 < d <= 1.2)."""
     p = params.cpu().numpy().astype(np.float64)
     st = status.cpu().numpy()
     c2 = chi2.cpu().numpy().astype(np.float64)
-    ok = (st == 0) & (p[:, 0] >= 0) & (p[:, 0] <= k - 1) & (p[:, 1] > 0) & (p[:, 1] < k) & \
-        (p[:, 2] > 0) & (p[:, 2] <= 1.5) & np.all(np.isfinite(p), axis=1)
+    ok = (st == 0) & (p[:, 0] >= 0) & (p[:, 0] <= k - 1) & (p[:, 1] > 1.0) & \
+        (p[:, 1] < 0.25 * k) & (p[:, 2] > 0.02) & (p[:, 2] <= 1.2) & \
+        np.all(np.isfinite(p), axis=1)
     mean = p[ok].mean(axis=0)
     std = p[ok].std(axis=0)
     noise = float(np.median(np.sqrt(np.maximum(c2[ok], 0.0) / (k - 4))))
     return mean.astype(np.float32), std.astype(np.float32), noise, ok
 
 
-def train(samples=1 << 20, epochs=12, batch=1024, lr=1e-3, holdout=1 << 16, out=DEFAULT_OUT,
+def train(samples=1 << 20, epochs=20, batch=1024, lr=1e-3, holdout=1 << 16, out=DEFAULT_OUT,
           log=print, workers=8):
     import torch
 
@@ -124,11 +127,14 @@ def train(samples=1 << 20, epochs=12, batch=1024, lr=1e-3, holdout=1 << 16, out=
     curve = []
     steps = samples // batch
     t1 = time.perf_counter()
+    total = epochs * steps
     for ep in range(epochs):
         perm = torch.from_numpy(rng.permutation(samples).astype(np.int32)).to(dev)
         acc = 0.0
         for s in range(steps):
-            tr.step(y, zt, wt, perm[s * batch:(s + 1) * batch], lr=lr, loss=loss)
+            frac = (ep * steps + s) / max(1, total - 1)
+            lr_t = 1e-5 + 0.5 * (lr - 1e-5) * (1.0 + np.cos(np.pi * frac))
+            tr.step(y, zt, wt, perm[s * batch:(s + 1) * batch], lr=lr_t, loss=loss)
             if s % 64 == 63:
                 acc += float(loss.item())
         curve.append(acc / max(1, steps // 64))
@@ -159,8 +165,9 @@ def holdout_report(plan, spec, n, dev, log=print):
 
     bt = synth.make_batch(spec, n, seed=4)
     fr = torch.from_numpy(bt.frames).to(dev)
-    cold = plan.process(fr, want=("params", "iters", "status"))
+    cold = plan.process(fr, want=("params", "iters", "status", "y"))
     warm = plan.process(fr, flags=FIT_WARM_MLP, want=("params", "iters", "status"))
+    p_net = plan.mlp_infer(cold["y"]).cpu().numpy()
     torch.cuda.synchronize(dev)
     reps = 5
     times = {}
@@ -176,7 +183,9 @@ def holdout_report(plan, spec, n, dev, log=print):
     sc, sw = cold["status"].cpu().numpy(), warm["status"].cpu().numpy()
     conv = sc == 0
     err = np.abs(pw[:, 0] - pc[:, 0]) / np.abs(pc[:, 1])
+    net_err = np.abs(p_net - pc) / np.abs(pc[:, 1:2])
     rep = {
+        "network_vs_cold_median_err_fwhm": [float(v) for v in np.median(net_err[conv], axis=0)],
         "frames": int(n),
         "cold_ms_per_batch": times["cold"], "warm_ms_per_batch": times["warm"],
         "speedup": times["cold"] / times["warm"],
@@ -195,7 +204,7 @@ def holdout_report(plan, spec, n, dev, log=print):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--samples", type=int, default=1 << 20)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--holdout", type=int, default=1 << 16)
