@@ -201,6 +201,7 @@ cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins
   CG_TRY(hipMemcpy(p->d_tw, tw.data(), sizeof(float2) * frame_len, hipMemcpyHostToDevice),
          "copy twiddles");
 #undef CG_TRY
+  p->fft_blocks = cg::fft_grid_limit(p);
   *out_plan = p;
   return CG_OK;
 }

@@ -20,8 +20,10 @@
 //   bank-conflict free.
 // * Twiddles come from a table of W_N^e built on the host in FP64 and rounded
 //   once to FP32 (no fast-math sin/cos on the device).
-// * Frames are independent: a partially filled last workgroup masks its
-//   loads and stores but keeps every barrier.
+// * Persistent blocks: the grid is sized to what fits on the chip, each block
+//   walks frame groups and prefetches the next group's samples into registers
+//   while it transforms the current one.  A partially filled last group masks
+//   its loads and stores but keeps every barrier.
 #include "internal.h"
 
 namespace cg {
@@ -132,142 +134,233 @@ struct FftShape {
   static constexpr int FPB = 256 / T;       // frames per 256-thread block
   static constexpr int PM = M + M / 16;     // padded plane length
   static constexpr int R3 = M / 256;        // radix of the last pass (1 = none)
+  static constexpr int NB3 = R3 > 1 ? 16 / R3 : 0;  // last-pass butterflies per thread
+  static constexpr size_t PLANE_BYTES = sizeof(float) * 2 * FPB * PM;
 };
 
+// Dynamic LDS: the real and imaginary planes of FPB frames, then one float4
+// per tooth {packed padded LDS offsets of Z[k] and Z[M-k], Re W_N^k, Im W_N^k,
+// 0.5 / ref}.
+template <int LOGM>
+size_t fft_lds_bytes(int k) {
+  return FftShape<LOGM>::PLANE_BYTES + sizeof(float4) * (size_t)k;
+}
+
+// Persistent form: the grid holds as many blocks as fit on the chip and each
+// block walks frame groups g = blockIdx.x, g + gridDim.x, ...  While a group
+// is transformed, the 64 bytes per thread of the next group are already in
+// flight (issued right after the current group's samples are converted), so
+// HBM sees a steady stream of loads instead of one burst per block.  Nothing
+// else is read from global memory inside the loop: twiddles live in
+// registers and the per-tooth constants in LDS, so waiting for one load never
+// means waiting for the prefetch.
 template <int LOGM>
 __global__ __launch_bounds__(256) void fft_teeth_kernel(
     const int32_t* __restrict__ frames, int64_t n_frames, const int32_t* __restrict__ bins,
     const float* __restrict__ half_inv_ref, const c32* __restrict__ tw, int k_teeth,
     float* __restrict__ out_mag, float* __restrict__ out_y, const int32_t* __restrict__ dev_n) {
   using S = FftShape<LOGM>;
-  constexpr int M = S::M, T = S::T, FPB = S::FPB, PM = S::PM, R3 = S::R3;
+  constexpr int M = S::M, T = S::T, FPB = S::FPB, PM = S::PM, R3 = S::R3, NB3 = S::NB3;
   constexpr int N = 2 * M;
-  __shared__ float s_re[FPB * PM];
-  __shared__ float s_im[FPB * PM];
+  extern __shared__ float4 lds4[];
+  float* s_re = reinterpret_cast<float*>(lds4);
+  float* s_im = s_re + FPB * PM;
+  float4* s_tooth = reinterpret_cast<float4*>(s_re + 2 * FPB * PM);
 
   if (dev_n) {
     const int64_t dn = *dev_n;
     n_frames = dn < n_frames ? dn : n_frames;
   }
+  const int64_t ngroups = (n_frames + FPB - 1) / FPB;
+  int64_t g = blockIdx.x;
+  if (g >= ngroups) return;  // uniform over the block
+
   const int tid = threadIdx.x;
   const int fl = tid / T;
   const int j = tid - fl * T;
-  const int64_t frame = (int64_t)blockIdx.x * FPB + fl;
-  const bool live = frame < n_frames;
   float* re = s_re + fl * PM;
   float* im = s_im + fl * PM;
 
-  // Padded LDS index padx(i) = i + i/16.  Each pass touches i = base + c*r
-  // with c a multiple of 16, so padx(base + c r) = padx(base) + (c + c/16) r:
-  // a per-thread base plus compile-time offsets.
-  c32 v[16];
-  // ---- pass 1: radix 16, Ns = 1, inputs straight from HBM ----
-  {
-    const int32_t* src = frames + frame * M + j;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      int32_t w = live ? __builtin_nontemporal_load(src + r * T) : 0;
-      v[r].x = (float)(int16_t)(w & 0xffff);
-      v[r].y = (float)(w >> 16);
-    }
-    dft16(v);
-    float* wr = re + 17 * j;  // padx(16 j + r) = 17 j + r
-    float* wi = im + 17 * j;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      wr[r] = v[r].x;
-      wi[r] = v[r].y;
-    }
-  }
-  __syncthreads();
-  // ---- pass 2: radix 16, Ns = 16 ----
-  {
-    constexpr int S2 = T + T / 16;
-    const float* rr = re + j + (j >> 4);
-    const float* ri = im + j + (j >> 4);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      v[r].x = rr[r * S2];
-      v[r].y = ri[r * S2];
-    }
-    __syncthreads();
-    const int jm = j & 15;
-    const int e2 = jm * (N / 256);  // pass-2 twiddle W_256^(jm r) = W_N^(e2 r)
-#pragma unroll
-    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw[e2 * r]);
-    dft16(v);
-    const int base = (j >> 4) * 256 + jm;
-    float* wr = re + base + (base >> 4);
-    float* wi = im + base + (base >> 4);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      wr[17 * r] = v[r].x;
-      wi[17 * r] = v[r].y;
-    }
-  }
-  __syncthreads();
-  // ---- pass 3: radix M/256, Ns = 256, 16/R3 butterflies per thread ----
-  if constexpr (R3 > 1) {
-    constexpr int NB = 16 / R3;
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int jp = j + T * q;
-      const float* rr = re + jp + (jp >> 4);
-      const float* ri = im + jp + (jp >> 4);
-#pragma unroll
-      for (int r = 0; r < R3; ++r) {
-        v[q * R3 + r].x = rr[272 * r];
-        v[q * R3 + r].y = ri[272 * r];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int jp = j + T * q;
-#pragma unroll
-      for (int r = 1; r < R3; ++r) v[q * R3 + r] = cmul(v[q * R3 + r], tw[2 * jp * r]);
-      dft_r<R3>(v + q * R3);
-      float* wr = re + jp + (jp >> 4);
-      float* wi = im + jp + (jp >> 4);
-#pragma unroll
-      for (int r = 0; r < R3; ++r) {
-        wr[272 * r] = v[q * R3 + r].x;
-        wi[272 * r] = v[q * R3 + r].y;
-      }
-    }
-    __syncthreads();
-  }
-  // ---- untangle the real spectrum at the tooth bins, amplitude, / ref ----
-  if (!live) return;
-  for (int i = j; i < k_teeth; i += T) {
+  // per-tooth constants
+  for (int i = tid; i < k_teeth; i += 256) {
     const int kb = bins[i];
     const int ia = kb & (M - 1);
     const int ib = (M - kb) & (M - 1);
-    const c32 a = {re[padx(ia)], im[padx(ia)]};
-    const c32 b = {re[padx(ib)], -im[padx(ib)]};  // conj Z[M-k]
-    const c32 s = cadd(a, b);
-    const c32 o = mul_mi(csub(a, b));
-    const c32 x = cadd(s, cmul(tw[kb], o));
-    const float r2 = __builtin_amdgcn_sqrtf(x.x * x.x + x.y * x.y);  // 2 |X[k]|
-    const int64_t idx = frame * k_teeth + i;
-    if (out_mag) out_mag[idx] = 0.5f * r2;
-    if (out_y) out_y[idx] = r2 * half_inv_ref[i];
+    const uint32_t packed = (uint32_t)padx(ia) | ((uint32_t)padx(ib) << 16);
+    const c32 w = tw[kb];
+    s_tooth[i] = make_float4(__uint_as_float(packed), w.x, w.y, half_inv_ref[i]);
   }
+  // twiddles of pass 2 (W_256^(jm r) = W_N^(e2 r)) and pass 3 (W_M^(jp r))
+  const int jm = j & 15;
+  const int e2 = jm * (N / 256);
+  c32 w2[15];
+#pragma unroll
+  for (int r = 1; r < 16; ++r) w2[r - 1] = tw[e2 * r];
+  c32 w3[NB3 > 0 ? NB3 * (R3 - 1) : 1];
+  if constexpr (R3 > 1) {
+#pragma unroll
+    for (int q = 0; q < NB3; ++q)
+#pragma unroll
+      for (int r = 1; r < R3; ++r) w3[q * (R3 - 1) + r - 1] = tw[2 * (j + T * q) * r];
+  }
+
+  // first group's samples.  Threads of frames past the end read the last
+  // frame instead (their results are never stored), so every load is
+  // unconditional.
+  const int64_t last = n_frames - 1;
+  int32_t raw[16];
+  {
+    int64_t frame = g * FPB + fl;
+    frame = frame < last ? frame : last;
+    const int32_t* src = frames + frame * M + j;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) raw[r] = __builtin_nontemporal_load(src + r * T);
+  }
+
+  for (; g < ngroups; g += gridDim.x) {
+    const int64_t frame = g * FPB + fl;
+    const bool live = frame < n_frames;
+    c32 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      v[r].x = (float)(int16_t)(raw[r] & 0xffff);
+      v[r].y = (float)(raw[r] >> 16);
+    }
+    // prefetch the next group of this block
+    {
+      int64_t fn = (g + gridDim.x) * FPB + fl;
+      fn = fn < last ? fn : last;
+      const int32_t* src = frames + fn * M + j;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) raw[r] = __builtin_nontemporal_load(src + r * T);
+    }
+
+    // ---- pass 1: radix 16, Ns = 1 ----
+    dft16(v);
+    __syncthreads();  // the previous group's epilogue has read the planes
+    {
+      float* wr = re + 17 * j;  // padx(16 j + r) = 17 j + r
+      float* wi = im + 17 * j;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        wr[r] = v[r].x;
+        wi[r] = v[r].y;
+      }
+    }
+    __syncthreads();
+    // ---- pass 2: radix 16, Ns = 16 ----
+    {
+      constexpr int S2 = T + T / 16;
+      const float* rr = re + j + (j >> 4);
+      const float* ri = im + j + (j >> 4);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        v[r].x = rr[r * S2];
+        v[r].y = ri[r * S2];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w2[r - 1]);
+      dft16(v);
+      const int base = (j >> 4) * 256 + jm;
+      float* wr = re + base + (base >> 4);
+      float* wi = im + base + (base >> 4);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        wr[17 * r] = v[r].x;
+        wi[17 * r] = v[r].y;
+      }
+    }
+    __syncthreads();
+    // ---- pass 3: radix M/256, Ns = 256 ----
+    if constexpr (R3 > 1) {
+#pragma unroll
+      for (int q = 0; q < NB3; ++q) {
+        const int jp = j + T * q;
+        const float* rr = re + jp + (jp >> 4);
+        const float* ri = im + jp + (jp >> 4);
+#pragma unroll
+        for (int r = 0; r < R3; ++r) {
+          v[q * R3 + r].x = rr[272 * r];
+          v[q * R3 + r].y = ri[272 * r];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NB3; ++q) {
+        const int jp = j + T * q;
+#pragma unroll
+        for (int r = 1; r < R3; ++r) v[q * R3 + r] = cmul(v[q * R3 + r], w3[q * (R3 - 1) + r - 1]);
+        dft_r<R3>(v + q * R3);
+        float* wr = re + jp + (jp >> 4);
+        float* wi = im + jp + (jp >> 4);
+#pragma unroll
+        for (int r = 0; r < R3; ++r) {
+          wr[272 * r] = v[q * R3 + r].x;
+          wi[272 * r] = v[q * R3 + r].y;
+        }
+      }
+      __syncthreads();
+    }
+    // ---- untangle the real spectrum at the tooth bins, amplitude, / ref ----
+    if (live) {
+      for (int i = j; i < k_teeth; i += T) {
+        const float4 t = s_tooth[i];
+        const uint32_t packed = __float_as_uint(t.x);
+        const int pa = (int)(packed & 0xffffu), pb = (int)(packed >> 16);
+        const c32 a = {re[pa], im[pa]};
+        const c32 b = {re[pb], -im[pb]};  // conj Z[M-k]
+        const c32 sm = cadd(a, b);
+        const c32 o = mul_mi(csub(a, b));
+        const c32 x = cadd(sm, cmul(c32{t.y, t.z}, o));
+        const float r2 = __builtin_amdgcn_sqrtf(x.x * x.x + x.y * x.y);  // 2 |X[k]|
+        const int64_t idx = frame * k_teeth + i;
+        if (out_mag) out_mag[idx] = 0.5f * r2;
+        if (out_y) out_y[idx] = r2 * t.w;
+      }
+    }
+  }
+}
+
+template <int LOGM>
+int max_blocks_t(const cg_plan* p) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fft_teeth_kernel<LOGM>, 256,
+                                                   fft_lds_bytes<LOGM>(p->k)) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
+          hipSuccess ||
+      per_cu <= 0 || cus <= 0)
+    return 0;
+  return per_cu * cus;
 }
 
 template <int LOGM>
 hipError_t launch_t(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
                     float* out_y, hipStream_t s, const int32_t* dev_n) {
   using S = FftShape<LOGM>;
-  const int64_t blocks = (nf + S::FPB - 1) / S::FPB;
+  int64_t blocks = (nf + S::FPB - 1) / S::FPB;
+  if (p->fft_blocks > 0 && blocks > p->fft_blocks) blocks = p->fft_blocks;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fft_teeth_kernel<LOGM>, dim3((unsigned)blocks), dim3(256), 0, s,
-                     reinterpret_cast<const int32_t*>(frames), nf, p->d_bins, p->d_half_inv_ref,
-                     reinterpret_cast<const c32*>(p->d_tw), p->k, out_mag, out_y, dev_n);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(fft_teeth_kernel<LOGM>, dim3((unsigned)blocks), dim3(256),
+                     fft_lds_bytes<LOGM>(p->k), s, reinterpret_cast<const int32_t*>(frames), nf,
+                     p->d_bins, p->d_half_inv_ref, reinterpret_cast<const c32*>(p->d_tw), p->k,
+                     out_mag, out_y, dev_n);
   return hipGetLastError();
 }
 
 }  // namespace
+
+int fft_grid_limit(const cg_plan* p) {
+  switch (p->m) {
+    case 256: return max_blocks_t<8>(p);
+    case 512: return max_blocks_t<9>(p);
+    case 1024: return max_blocks_t<10>(p);
+    case 2048: return max_blocks_t<11>(p);
+    case 4096: return max_blocks_t<12>(p);
+    default: return 0;
+  }
+}
 
 hipError_t launch_fft_teeth(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
                             float* out_y, hipStream_t s, const int32_t* dev_n) {

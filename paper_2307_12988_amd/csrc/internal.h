@@ -29,6 +29,7 @@ struct cg_plan {
   size_t ws_bytes = 0;
   cg_mlp* mlp = nullptr;
   int32_t lm_chunk = 0;        // spectra per wave in the fit kernel (0 = auto)
+  int32_t fft_blocks = 0;      // resident blocks of the FFT kernel on the device (0 = no cap)
   // tooth-DFT bases for the matrix-core forms, [ceil(k/64)*64][n], built on
   // first use: bf16 cos_hi, cos_lo, sin_hi, sin_lo / fp16 cos, sin
   uint16_t* d_mfma_bf[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -50,6 +51,8 @@ void set_detail(const std::string& s);
 // Every launch helper takes an optional dev_n: a device int32 frame count
 // read by the kernels at run time (at most n_frames, the capacity the grid is
 // sized for), so one captured graph serves bursts of any size.
+// Blocks of the persistent FFT kernel that fit on the plan's device at once.
+int fft_grid_limit(const cg_plan* p);
 hipError_t launch_fft_teeth(const cg_plan* p, const int16_t* frames, int64_t n_frames,
                             float* out_mag, float* out_y, hipStream_t s,
                             const int32_t* dev_n = nullptr);
