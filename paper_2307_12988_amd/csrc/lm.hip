@@ -59,79 +59,126 @@ __device__ __forceinline__ double rsq_d(double x) {
   return r;
 }
 
+// One Newton step on the hardware reciprocal: the per-tooth denominators are
+// >= 1 and the hardware estimate is good to far more than half the FP64
+// mantissa, so one step leaves an error well below what the FP64 residuals
+// need.
+__device__ __forceinline__ double rcp1_d(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Sums over the group's teeth at one parameter point (Q = ceil(k / 16) slots
+// per lane).  The arithmetic is the same for every lane; teeth past the last
+// one, which only the last slot can hold, contribute exact zeros, and a
+// group whose point is not used (idle, or a rejected trial point) simply
+// computes values nobody reads, so the loop body has no divergent branches.
+//
+// The Jacobian columns share per-spectrum factors, which are applied once to
+// the reduced sums instead of to every tooth: with u = 2 (x - c) / w,
+// D = 1 + u^2, s = d / D^2,
+//   df/dc = (-4 b / w) s u,   df/dw = (-2 b / w) s u^2,
+//   df/dd = (-b) / D,         df/db = 1 - d / D.
 template <int Q>
-__device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, bool live, double c,
-                                         double w, double d, double b, Sums& s) {
-  const int gl = lane_id() & 15;
+__device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, double c, double w,
+                                         double d, double b, Sums& s) {
+  int gl = lane_id() & 15;
+  asm volatile("" : "+v"(gl));  // slot indices are rebuilt per call, not kept live
   float acc[14];
 #pragma unroll
   for (int j = 0; j < 14; ++j) acc[j] = 0.0f;
   double chi2 = 0.0;
   const double two_iw = 2.0 * rcp_d(w);
-  const float two_iwf = (float)two_iw;
-  const float four_iwf = 2.0f * two_iwf;
-  const float bf = (float)b;
+  const double c_iw = c * two_iw;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int i = gl + 16 * q;
-    if (live && i < k) {
-      const double u = ((double)i - c) * two_iw;
-      const double den = fma(u, u, 1.0);
-      const double inv = rcp_d(den);
-      const double qd = d * inv;
-      const double f = fma(-b, qd, b);
-      const double r = (double)yv[q] - f;
-      chi2 = fma(r, r, chi2);
-      const float uf = (float)u, invf = (float)inv, qf = (float)qd, rf = (float)r;
-      const float t = bf * qf * invf;          // b d / D^2
-      const float jc = -t * uf * four_iwf;     // -4 b d u / (w D^2)
-      const float jw = -t * uf * uf * two_iwf; // -2 b d u^2 / (w D^2)
-      const float jd = -bf * invf;             // -b / D
-      const float jb = 1.0f - qf;              // 1 - d / D
-      acc[0] += jc * jc;
-      acc[1] += jc * jw;
-      acc[2] += jc * jd;
-      acc[3] += jc * jb;
-      acc[4] += jw * jw;
-      acc[5] += jw * jd;
-      acc[6] += jw * jb;
-      acc[7] += jd * jd;
-      acc[8] += jd * jb;
-      acc[9] += jb * jb;
-      acc[10] += jc * rf;
-      acc[11] += jw * rf;
-      acc[12] += jd * rf;
-      acc[13] += jb * rf;
+    // The empty asm statements pin the slots in program order: each slot's
+    // index passes through one before its arithmetic and its sums pass
+    // through one after it.  Left alone, the compiler evaluates the FP64 part
+    // of every slot first and keeps all of it live (about 100 extra VGPRs).
+    int i = gl + 16 * q;
+    asm volatile("" : "+v"(i));
+    const double u = fma((double)i, two_iw, -c_iw);
+    const double den = fma(u, u, 1.0);
+    const double inv = rcp1_d(den);
+    const double qd = d * inv;
+    const double f = fma(-b, qd, b);
+    double r = (double)yv[q] - f;
+    const float uf = (float)u, invf = (float)inv, qf = (float)qd;
+    float jc = qf * invf * uf;   // s u
+    float jw = jc * uf;          // s u^2
+    float jd = invf;             // 1 / D
+    float jb = 1.0f - qf;        // 1 - d / D
+    if (q == Q - 1) {            // only the last slot can be partial
+      const bool in = i < k;
+      r = in ? r : 0.0;
+      jc = in ? jc : 0.0f;
+      jw = in ? jw : 0.0f;
+      jd = in ? jd : 0.0f;
+      jb = in ? jb : 0.0f;
     }
+    const float rf = (float)r;
+    chi2 = fma(r, r, chi2);
+    acc[0] = fmaf(jc, jc, acc[0]);
+    acc[1] = fmaf(jc, jw, acc[1]);
+    acc[2] = fmaf(jc, jd, acc[2]);
+    acc[3] = fmaf(jc, jb, acc[3]);
+    acc[4] = fmaf(jw, jw, acc[4]);
+    acc[5] = fmaf(jw, jd, acc[5]);
+    acc[6] = fmaf(jw, jb, acc[6]);
+    acc[7] = fmaf(jd, jd, acc[7]);
+    acc[8] = fmaf(jd, jb, acc[8]);
+    acc[9] = fmaf(jb, jb, acc[9]);
+    acc[10] = fmaf(jc, rf, acc[10]);
+    acc[11] = fmaf(jw, rf, acc[11]);
+    acc[12] = fmaf(jd, rf, acc[12]);
+    acc[13] = fmaf(jb, rf, acc[13]);
+    asm volatile(""
+                 : "+v"(chi2), "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]),
+                   "+v"(acc[4]), "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]),
+                   "+v"(acc[9]), "+v"(acc[10]), "+v"(acc[11]), "+v"(acc[12]), "+v"(acc[13]));
   }
+  float sum[14];
 #pragma unroll
-  for (int j = 0; j < 10; ++j) s.a[j] = sum16(acc[j]);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) s.g[j] = sum16(acc[10 + j]);
+  for (int j = 0; j < 14; ++j) sum[j] = sum16(acc[j]);
+  // column factors: c, w, d carry al, be, ga; b carries 1
+  const float bf = (float)b, two_iwf = (float)two_iw;
+  const float al = -2.0f * bf * two_iwf, be = -bf * two_iwf, ga = -bf;
+  s.a[0] = sum[0] * (al * al);
+  s.a[1] = sum[1] * (al * be);
+  s.a[2] = sum[2] * (al * ga);
+  s.a[3] = sum[3] * al;
+  s.a[4] = sum[4] * (be * be);
+  s.a[5] = sum[5] * (be * ga);
+  s.a[6] = sum[6] * be;
+  s.a[7] = sum[7] * (ga * ga);
+  s.a[8] = sum[8] * ga;
+  s.a[9] = sum[9];
+  s.g[0] = sum[10] * al;
+  s.g[1] = sum[11] * be;
+  s.g[2] = sum[12] * ga;
+  s.g[3] = sum[13];
   s.chi2 = sum16(chi2);
 }
 
 // Solve (A + lam diag A) delta = g by Cholesky in FP64; false if the damped
-// matrix is not positive definite.
+// matrix is not positive definite or the step is not finite.  Straight-line
+// code: a failed pivot turns into NaNs that the final test rejects.
 __device__ __forceinline__ bool damped_solve(const Sums& s, double lam, double (&delta)[4]) {
   const double sc = 1.0 + lam;
   const double a00 = (double)s.a[0] * sc, a01 = s.a[1], a02 = s.a[2], a03 = s.a[3];
   const double a11 = (double)s.a[4] * sc, a12 = s.a[5], a13 = s.a[6];
   const double a22 = (double)s.a[7] * sc, a23 = s.a[8];
   const double a33 = (double)s.a[9] * sc;
-  if (!(a00 > 0.0)) return false;
   const double i00 = rsq_d(a00);
   const double l10 = a01 * i00, l20 = a02 * i00, l30 = a03 * i00;
   const double t11 = a11 - l10 * l10;
-  if (!(t11 > 0.0)) return false;
   const double i11 = rsq_d(t11);
   const double l21 = (a12 - l20 * l10) * i11, l31 = (a13 - l30 * l10) * i11;
   const double t22 = a22 - l20 * l20 - l21 * l21;
-  if (!(t22 > 0.0)) return false;
   const double i22 = rsq_d(t22);
   const double l32 = (a23 - l30 * l20 - l31 * l21) * i22;
   const double t33 = a33 - l30 * l30 - l31 * l31 - l32 * l32;
-  if (!(t33 > 0.0)) return false;
   const double i33 = rsq_d(t33);
   const double z0 = (double)s.g[0] * i00;
   const double z1 = ((double)s.g[1] - l10 * z0) * i11;
@@ -141,7 +188,9 @@ __device__ __forceinline__ bool damped_solve(const Sums& s, double lam, double (
   delta[2] = (z2 - l32 * delta[3]) * i22;
   delta[1] = (z1 - l21 * delta[2] - l31 * delta[3]) * i11;
   delta[0] = (z0 - l10 * delta[1] - l20 * delta[2] - l30 * delta[3]) * i00;
-  return isfinite(delta[0]) && isfinite(delta[1]) && isfinite(delta[2]) && isfinite(delta[3]);
+  const bool pd = a00 > 0.0 && t11 > 0.0 && t22 > 0.0 && t33 > 0.0;
+  return pd && isfinite(delta[0]) && isfinite(delta[1]) && isfinite(delta[2]) &&
+         isfinite(delta[3]);
 }
 
 template <int Q>
@@ -151,7 +200,7 @@ __device__ __forceinline__ void load_spectrum(const float* __restrict__ y, int64
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int i = gl + 16 * q;
-    yv[q] = i < k ? y[s * k + i] : 0.0f;
+    yv[q] = (q < Q - 1 || i < k) ? y[s * k + i] : 0.0f;  // only the last slot can be partial
   }
 }
 
@@ -200,59 +249,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   }
 
   while (__ballot(active) != 0ull) {
-    // 1. damped step for groups past their start point
-    double delta[4] = {0.0, 0.0, 0.0, 0.0};
-    bool solved = false;
-    if (active && !fresh) solved = damped_solve(cur, lam, delta);
-    const double tc = c + delta[0], tw = w + delta[1], td = d + delta[2], tb = b + delta[3];
+    // 1. damped step for groups past their start point (every group runs the
+    //    solve; only those past their start point use it)
+    const bool stepping = active && !fresh;
+    double delta[4];
+    const bool solved = damped_solve(cur, lam, delta) && stepping;
+    const double tc = stepping ? c + delta[0] : c, tw = stepping ? w + delta[1] : w;
+    const double td = stepping ? d + delta[2] : d, tb = stepping ? b + delta[3] : b;
     const bool point_ok = fresh || (solved && isfinite(tc) && isfinite(tw) && isfinite(td) &&
                                     isfinite(tb) && tw > 0.0);
     // 2. evaluation (start point for fresh groups, trial point otherwise)
     Sums trial;
-    evaluate<Q>(yv, k, active && point_ok, tc, tw, td, tb, trial);
-    // 3. decisions
-    bool done = false;
-    int st = CG_FIT_MAX_ITER;
-    if (active) {
-      if (fresh) {
-        fresh = false;
-        cur = trial;
-        it = 0;
-        lam = 1e-3;
-        if (!isfinite(cur.chi2)) {
-          done = true;
-          st = CG_FIT_SINGULAR;
-        } else if (cur.chi2 <= 1e-30) {
-          done = true;
-          st = CG_FIT_CONVERGED;
-        }
-      } else {
-        ++it;
-        if (!solved) {
-          done = true;
-          st = CG_FIT_SINGULAR;
-        } else if (point_ok && isfinite(trial.chi2) && trial.chi2 <= cur.chi2) {
-          const double old = cur.chi2;
-          const double drop = old - trial.chi2;
-          c = tc;
-          w = tw;
-          d = td;
-          b = tb;
-          cur = trial;
-          lam *= 0.1;
-          if (drop <= 1e-6 * old || cur.chi2 <= 1e-30) {
-            done = true;
-            st = CG_FIT_CONVERGED;
-          }
-        } else {
-          lam *= 10.0;
-        }
-        if (!done && it >= max_iter) {
-          done = true;
-          st = CG_FIT_MAX_ITER;
-        }
-      }
-    }
+    evaluate<Q>(yv, k, tc, tw, td, tb, trial);
+    // 3. decisions, as selects: the four groups of a wave are in different
+    //    states, and branches here would only execute every path with copies
+    const bool start = active && fresh;
+    const bool accept = stepping && solved && point_ok && isfinite(trial.chi2) &&
+                        trial.chi2 <= cur.chi2;
+    const bool take = start || accept;
+    const double old = cur.chi2;
+    it = start ? 0 : (stepping ? it + 1 : it);
+    lam = start ? 1e-3 : (accept ? lam * 0.1 : ((stepping && solved) ? lam * 10.0 : lam));
+    c = take ? tc : c;
+    w = take ? tw : w;
+    d = take ? td : d;
+    b = take ? tb : b;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) cur.a[j] = take ? trial.a[j] : cur.a[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cur.g[j] = take ? trial.g[j] : cur.g[j];
+    cur.chi2 = take ? trial.chi2 : cur.chi2;
+    fresh = active ? false : fresh;
+    const bool start_bad = start && !isfinite(trial.chi2);
+    const bool start_exact = start && !start_bad && trial.chi2 <= 1e-30;
+    const bool singular = stepping && !solved;
+    const bool conv = accept && (old - trial.chi2 <= 1e-6 * old || trial.chi2 <= 1e-30);
+    const bool capped = stepping && !singular && !conv && it >= max_iter;
+    const bool done = start_bad || start_exact || singular || conv || capped;
+    const int st = (start_bad || singular) ? CG_FIT_SINGULAR
+                                           : ((start_exact || conv) ? CG_FIT_CONVERGED
+                                                                    : CG_FIT_MAX_ITER);
     // 4. finished groups report and take the next spectrum of the chunk
     if (done && gl == 0) {
       if (params) {
@@ -330,6 +366,41 @@ int lm_chunk(int64_t nf) {
   return (int)c;
 }
 
+// The fit kernel is instantiated for every slot count Q = ceil(k / 16), so
+// only its last slot needs masking.
+#define CG_LM_SWITCH(k, CALL)                                                            \
+  switch (((k) + 15) / 16) {                                                             \
+    case 1: { constexpr int Q = 1; CALL; } break;                                        \
+    case 2: { constexpr int Q = 2; CALL; } break;                                        \
+    case 3: { constexpr int Q = 3; CALL; } break;                                        \
+    case 4: { constexpr int Q = 4; CALL; } break;                                        \
+    case 5: { constexpr int Q = 5; CALL; } break;                                        \
+    case 6: { constexpr int Q = 6; CALL; } break;                                        \
+    case 7: { constexpr int Q = 7; CALL; } break;                                        \
+    case 8: { constexpr int Q = 8; CALL; } break;                                        \
+    case 9: { constexpr int Q = 9; CALL; } break;                                        \
+    case 10: { constexpr int Q = 10; CALL; } break;                                      \
+    case 11: { constexpr int Q = 11; CALL; } break;                                      \
+    case 12: { constexpr int Q = 12; CALL; } break;                                      \
+    case 13: { constexpr int Q = 13; CALL; } break;                                      \
+    case 14: { constexpr int Q = 14; CALL; } break;                                      \
+    case 15: { constexpr int Q = 15; CALL; } break;                                      \
+    case 16: { constexpr int Q = 16; CALL; } break;                                      \
+    case 17: { constexpr int Q = 17; CALL; } break;                                      \
+    case 18: { constexpr int Q = 18; CALL; } break;                                      \
+    case 19: { constexpr int Q = 19; CALL; } break;                                      \
+    case 20: { constexpr int Q = 20; CALL; } break;                                      \
+    case 21: { constexpr int Q = 21; CALL; } break;                                      \
+    case 22: { constexpr int Q = 22; CALL; } break;                                      \
+    case 23: { constexpr int Q = 23; CALL; } break;                                      \
+    case 24: { constexpr int Q = 24; CALL; } break;                                      \
+    case 25: { constexpr int Q = 25; CALL; } break;                                      \
+    case 26: { constexpr int Q = 26; CALL; } break;                                      \
+    case 27: { constexpr int Q = 27; CALL; } break;                                      \
+    case 28: { constexpr int Q = 28; CALL; } break;                                      \
+    default: return hipErrorInvalidValue;                                                \
+  }
+
 hipError_t launch_lm(const float* y, const float* p0, int64_t nf, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
                      int chunk, const int32_t* dev_n) {
@@ -337,7 +408,7 @@ hipError_t launch_lm(const float* y, const float* p0, int64_t nf, int k, int max
   const int64_t waves = (nf + chunk - 1) / chunk;
   const int64_t blocks = (waves + 3) / 4;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  CG_DISPATCH_Q16(k, hipLaunchKernelGGL(lm_kernel<Q>, dim3((unsigned)blocks), dim3(256), 0, s, y,
+  CG_LM_SWITCH(k, hipLaunchKernelGGL(lm_kernel<Q>, dim3((unsigned)blocks), dim3(256), 0, s, y,
                                         p0, nullptr, dev_n, nf, k, max_iter, chunk, params,
                                         iters, status, chi2, -1));
   return hipGetLastError();
@@ -351,7 +422,7 @@ hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx
   const int64_t waves = (n_cap + chunk - 1) / chunk;
   const int64_t blocks = (waves + 3) / 4;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  CG_DISPATCH_Q16(k, hipLaunchKernelGGL(lm_kernel<Q>, dim3((unsigned)blocks), dim3(256), 0, s, y,
+  CG_LM_SWITCH(k, hipLaunchKernelGGL(lm_kernel<Q>, dim3((unsigned)blocks), dim3(256), 0, s, y,
                                         p0, idx, count, n_cap, k, max_iter, chunk, params, iters,
                                         status, chi2, status_code));
   return hipGetLastError();

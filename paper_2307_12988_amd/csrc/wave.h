@@ -71,6 +71,31 @@ __device__ __forceinline__ uint64_t min16(uint64_t v) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t min16(uint32_t v) {
+  uint32_t o;
+  o = (uint32_t)dpp_i<0xB1>((int)v);
+  v = o < v ? o : v;
+  o = (uint32_t)dpp_i<0x4E>((int)v);
+  v = o < v ? o : v;
+  o = (uint32_t)dpp_i<0x141>((int)v);
+  v = o < v ? o : v;
+  o = (uint32_t)dpp_i<0x140>((int)v);
+  v = o < v ? o : v;
+  return v;
+}
+__device__ __forceinline__ uint32_t max16(uint32_t v) {
+  uint32_t o;
+  o = (uint32_t)dpp_i<0xB1>((int)v);
+  v = o > v ? o : v;
+  o = (uint32_t)dpp_i<0x4E>((int)v);
+  v = o > v ? o : v;
+  o = (uint32_t)dpp_i<0x141>((int)v);
+  v = o > v ? o : v;
+  o = (uint32_t)dpp_i<0x140>((int)v);
+  v = o > v ? o : v;
+  return v;
+}
+
 // Order-preserving map of float bits to unsigned (negatives below positives).
 __device__ __forceinline__ uint32_t float_key(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -85,7 +110,7 @@ __device__ __forceinline__ float key_float(uint32_t k) {
 // computed by a group of 16 lanes.  Lane gl of the group holds row values
 // i = gl + 16 q (q < Q), masked beyond k.
 //   c0 = first index of the minimum; b0 = lower median (order statistic
-//   (k-1)/2, by a 32-step radix select on order-preserving keys);
+//   (k-1)/2, by bisection over order-preserving keys);
 //   d0 = clip(1 - M[c0]/b0, 0.05, 0.95), 0.05 if b0 <= 0;
 //   w0 = max(2, #{M < b0 (1 - d0/2)}).
 // The arithmetic that decides d0 and the count uses IEEE float32 operations in
@@ -99,7 +124,7 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int i = gl + 16 * q;
-    keys[q] = float_key(mv[q]);
+    keys[q] = float_key(mv[q] + 0.0f);  // -0 -> +0: equal values, equal keys
     const uint64_t cand = ((uint64_t)keys[q] << 32) | (uint32_t)i;
     if (i < k && cand < best) best = cand;
   }
@@ -107,23 +132,46 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
   const int besti = (int)(uint32_t)best;
   const float bestv = key_float((uint32_t)(best >> 32));
 
-  int rank = (k - 1) / 2;
-  uint32_t prefix = 0u, himask = 0u;
-  for (int bit = 31; bit >= 0; --bit) {
-    const uint32_t b = 1u << bit;
+  // Lower median (order statistic r = (k-1)/2) by bisection over the key
+  // interval [lo, hi], which always holds the answer; c_lo = #{keys < lo},
+  // c_hi = #{keys <= hi}.  When the interval holds a single key the answer is
+  // the smallest key >= lo.
+  const int r = (k - 1) / 2;
+  uint32_t lo = (uint32_t)(best >> 32), hi = 0u;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int i = gl + 16 * q;
+    if (i < k) hi = keys[q] > hi ? keys[q] : hi;
+  }
+  hi = max16(hi);
+  int c_lo = 0, c_hi = k;
+  while (lo < hi && c_hi - c_lo > 1) {
+    const uint32_t mid = lo + ((hi - lo) >> 1) + 1u;  // lo < mid <= hi
     int c = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int i = gl + 16 * q;
-      c += (i < k) && (((keys[q] ^ prefix) & himask) == 0u) && !(keys[q] & b);
+      c += (i < k) && (keys[q] < mid);
     }
     c = sum16(c);
-    if (rank >= c) {
-      prefix |= b;
-      rank -= c;
+    if (c <= r) {
+      lo = mid;
+      c_lo = c;
+    } else {
+      hi = mid - 1u;
+      c_hi = c;
     }
-    himask |= b;
   }
+  if (lo < hi) {
+    uint32_t m = 0xffffffffu;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int i = gl + 16 * q;
+      if (i < k && keys[q] >= lo && keys[q] < m) m = keys[q];
+    }
+    lo = min16(m);
+  }
+  const uint32_t prefix = lo;
   const float med = key_float(prefix);
   float d;
   if (med > 0.0f) {

@@ -112,6 +112,24 @@ def test_init_bit_exact_on_same_float32_input(nf, k):
     assert np.array_equal(p0.cpu().numpy(), oracle.initial_guess(y))
 
 
+@pytest.mark.parametrize("levels", [1, 3, 17])
+def test_init_bit_exact_with_repeated_and_signed_values(levels):
+    """Rows made of a few repeated values, negatives and zeros included: the
+    lower median is selected among equal keys and across the sign boundary."""
+    _say(f"init repeated values levels={levels}")
+    rng = np.random.default_rng(100 + levels)
+    nf, k = 96, 220
+    vals = np.linspace(-0.5, 1.5, levels).astype(np.float32)
+    y = vals[rng.integers(0, levels, (nf, k))]
+    y[5] = 0.0
+    y[6, ::2] = -0.0
+    plan = cg.Plan(2048, 1e9, np.arange(1, k + 1), np.ones(k))
+    p0, med = plan.init_spectra(torch.from_numpy(y).to(DEV), want_median=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(med.cpu().numpy(), oracle.median7x7(y))
+    assert np.array_equal(p0.cpu().numpy(), oracle.initial_guess(y))
+
+
 def test_median_filter_and_start_points_separately():
     rng = np.random.default_rng(8)
     nf, k = 45, 220
