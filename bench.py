@@ -216,6 +216,92 @@ def precision_forms(args, torch, cg, dev):
     plan.close()
 
 
+def warm_forms(args, torch, cg, dev):
+    """The learned warm start beside the plain cold-start path on the same
+    frames: spectra of the network's training distribution (a seed used for
+    neither training nor hold-out), whole path per batch.  Forms: cold (7x7
+    median start point + LM <= 20 iterations), warm with the 2-iteration
+    polish, and warm with the polish run to convergence (<= 20 iterations);
+    the warm forms fall back to the cold start when the polished fit's RMS
+    residual exceeds twice the noise floor.  Accuracy: centre difference to
+    the cold fit over the first batch, and to the FP64 oracle on a sample."""
+    spec = synth.spec_learned()
+    nf, n, k = args.frames, spec.n, spec.k
+    weights = os.path.join(ROOT, "paper_2307_12988_amd", "data", "warmstart_learned.npz")
+    w = np.load(weights)
+    _log(f"generating {args.pool} batches of {nf} x {n} int16 (learned distribution) ...")
+    pool_np, ref_np = make_pool(spec, nf, args.pool, workers=args.pool)
+    pool = [torch.from_numpy(fr).to(dev) for fr in pool_np]
+    plan = cg.Plan(n, spec.fs, spec.bins, np.ones(k, dtype=np.float32))
+    ref_gpu = plan.reference_from_frames(torch.from_numpy(ref_np).to(dev)).cpu().numpy()
+    plan.set_reference(ref_gpu)
+    plan.set_mlp(w["params"], w["out_mean"], w["out_std"], float(w["noise_floor"]))
+    ws = torch.empty(plan.workspace_bytes(nf), dtype=torch.uint8, device=dev)
+    params = torch.empty((nf, 4), dtype=torch.float32, device=dev)
+    iters = torch.empty((nf,), dtype=torch.int32, device=dev)
+    status = torch.empty((nf,), dtype=torch.int32, device=dev)
+    forms = [("cold", cg.FIT_COLD, 2), ("warm_polish2", cg.FIT_WARM_MLP, 2),
+             ("warm_polish20", cg.FIT_WARM_MLP, 20)]
+    res = {}
+    for name, flag, polish in forms:
+        plan.set_polish_iters(polish)
+        for i in range(args.warmup):
+            plan.process(pool[i % len(pool)], params=params, workspace=ws, flags=flag, want=())
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            plan.process(pool[i % len(pool)], params=params, workspace=ws, flags=flag, want=())
+        torch.cuda.synchronize(dev)
+        wall = time.perf_counter() - t0
+        plan.process(pool[0], params=params, iters=iters, status=status, workspace=ws,
+                     flags=flag, want=())
+        torch.cuda.synchronize(dev)
+        res[name] = {"wall": wall, "params": params.cpu().numpy().copy(),
+                     "iters": iters.cpu().numpy().copy(), "status": status.cpu().numpy().copy()}
+    cold = res["cold"]
+    conv = cold["status"] == 0
+    orc = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ns = min(args.cpu_frames, 4096, nf)
+        t0 = time.perf_counter()
+        ref_or = oracle.reference_spectrum(ref_np, spec.bins)
+        out = oracle.process_batch(pool_np[0][:ns], spec.bins, ref_or)
+        dt = time.perf_counter() - t0
+        orc = {"params": out["params"], "status": out["status"], "n": ns, "dt": dt}
+    for name, flag, polish in forms:
+        r = res[name]
+        err = np.abs(r["params"][:, 0] - cold["params"][:, 0]) / np.abs(cold["params"][:, 1])
+        line = {"metric": METRIC, "value": nf * n * 2 * args.steps / r["wall"] / 1e9,
+                "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "ms_per_step": r["wall"] / args.steps * 1e3, "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                "config": {"workload": f"learned warm start, form {name}: {nf} frames x {n} int16 "
+                                       f"samples, {k} teeth, centre +-40 teeth, FWHM 3-20, depth "
+                                       f"0.1-0.9, SNR 15-50 dB, baseline tilt +-5%",
+                           "form": name, "polish_iters": polish if flag == cg.FIT_WARM_MLP else None},
+                "spectra_per_s": nf * args.steps / r["wall"],
+                "speedup_vs_cold": res["cold"]["wall"] / r["wall"],
+                "mean_iters": float(r["iters"].mean()),
+                "status_counts": np.bincount(r["status"], minlength=4).tolist(),
+                "centre_vs_cold": {"frames": int(conv.sum()),
+                                   "within_1e-3_fwhm": float(np.mean(err[conv] <= 1e-3)),
+                                   "median_fwhm": float(np.median(err[conv]))}}
+        if orc is not None:
+            m = orc["n"] - 3  # the oracle's slice ends at its own last frame
+            oc = orc["status"][:m] == 0
+            eo = np.abs(r["params"][:m, 0] - orc["params"][:m, 0]) / np.abs(orc["params"][:m, 1])
+            line["centre_vs_oracle"] = {"frames": int(oc.sum()),
+                                        "within_1e-3_fwhm": float(np.mean(eo[oc] <= 1e-3)),
+                                        "median_fwhm": float(np.median(eo[oc]))}
+            line["cpu_baseline"] = {"value": orc["n"] * n * 2 / orc["dt"] / 1e9, "unit": "GB/s",
+                                    "cores": None, "kind": "oracle",
+                                    "sample": f"cold-start FP64 oracle on the first {orc['n']} "
+                                              f"frames of batch 0, {orc['dt']:.1f} s"}
+        print(json.dumps(line), flush=True)
+    plan.close()
+
+
 def multistream(args, torch, cg, dev):
     """16 concurrent streams (frame lengths 512..8192, 64..440 teeth, own
     reference, dip parameters and noise floor) through the ring pipeline with
@@ -335,7 +421,7 @@ def main():
     ap.add_argument("--frames", type=int, default=65536)
     ap.add_argument("--cpu-frames", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["paper_rate", "precision", "multistream"],
+    ap.add_argument("--workload", choices=["paper_rate", "precision", "multistream", "warm"],
                     default="paper_rate",
                     help="paper_rate: the headline line; precision: 131072 x 4096 frames, one "
                          "line per tooth-DFT form (FFT and the three matrix-core forms); "
@@ -369,6 +455,8 @@ def main():
         torch.cuda.synchronize(dev)
         print(json.dumps({"calibrate_copy_bytes": 1 << 30, "copies": 5}), flush=True)
         return
+    if args.workload == "warm":
+        return warm_forms(args, torch, cg, dev)
     if args.workload == "precision":
         return precision_forms(args, torch, cg, dev)
     if args.workload == "multistream":

@@ -238,6 +238,13 @@ cg_status cg_fit_spectra(cg_plan* plan, const float* y, const float* p0, int64_t
 cg_status cg_set_mlp(cg_plan* plan, const float* params, const float* out_mean,
                      const float* out_std, float noise_floor);
 
+/* Levenberg-Marquardt iterations run from the network's start point before
+ * the residual test (paper's learned part: a short polish of one or two
+ * iterations).  iters in 1..CG_MAX_ITER; the default is 2.  With 20, the
+ * cold start's cap, the polish is a full fit from the network's start point.
+ * Errors: CG_ERR_INVALID_ARG out of range. */
+cg_status cg_set_polish_iters(cg_plan* plan, int32_t iters);
+
 /* Network start points only: y device float32 [n_frames][n_teeth] -> out_p0
  * device float32 [n_frames][4] (CG_ERR_STATE before cg_set_mlp). */
 cg_status cg_mlp_infer(cg_plan* plan, const float* y, int64_t n_frames, float* out_p0,

@@ -304,8 +304,8 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
     float* chi2 = out_chi2 ? out_chi2 : chi2_ws;
     e = cg::launch_mlp_infer(p->mlp, y, nf, p->k, p0, s);
     if (e == hipSuccess)
-      e = cg::launch_lm(y, p0, nf, p->k, 2, out_params, out_iters, out_status, chi2, s,
-                        p->lm_chunk);
+      e = cg::launch_lm(y, p0, nf, p->k, p->polish_iters, out_params, out_iters, out_status,
+                        chi2, s, p->lm_chunk);
     if (e == hipSuccess)
       e = cg::launch_fallback_select(chi2, nf, p->k, p->mlp->noise_floor, fb_flags, fb_idx,
                                      fb_count, s);
@@ -483,6 +483,13 @@ cg_status cg_mlp_get_params(cg_mlp_trainer* t, float* params) {
   if (e == hipSuccess)
     e = hipMemcpy(params, t->params, sizeof(float) * CG_MLP_NPARAMS, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "cg_mlp_get_params");
+  return CG_OK;
+}
+
+cg_status cg_set_polish_iters(cg_plan* p, int32_t iters) {
+  if (!p) return CG_ERR_NULL;
+  if (iters < 1 || iters > CG_MAX_ITER) return CG_ERR_INVALID_ARG;
+  p->polish_iters = iters;
   return CG_OK;
 }
 

@@ -29,6 +29,7 @@ struct cg_plan {
   size_t ws_bytes = 0;
   cg_mlp* mlp = nullptr;
   int32_t lm_chunk = 0;        // spectra per wave in the fit kernel (0 = auto)
+  int32_t polish_iters = 2;    // LM iterations from the network's start point
   int32_t fft_blocks = 0;      // resident blocks of the FFT kernel on the device (0 = no cap)
   // tooth-DFT bases for the matrix-core forms, [ceil(k/64)*64][n], built on
   // first use: bf16 cos_hi, cos_lo, sin_hi, sin_lo / fp16 cos, sin

@@ -128,8 +128,8 @@ hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
   if ((ps.flags & CG_FIT_MASK) == CG_FIT_WARM_MLP) {
     if (le == hipSuccess) le = launch_mlp_infer(p->mlp, sl.y, cap, p->k, sl.p0, s, sl.n_dev);
     if (le == hipSuccess)
-      le = launch_lm(sl.y, sl.p0, cap, p->k, 2, sl.params, sl.iters, sl.status, sl.chi2, s,
-                     p->lm_chunk, sl.n_dev);
+      le = launch_lm(sl.y, sl.p0, cap, p->k, p->polish_iters, sl.params, sl.iters, sl.status,
+                     sl.chi2, s, p->lm_chunk, sl.n_dev);
     if (le == hipSuccess)
       le = launch_fallback_select(sl.chi2, cap, p->k, p->mlp->noise_floor, sl.fb_flags, sl.fb_idx,
                                   sl.fb_count, s, sl.n_dev);

@@ -221,6 +221,11 @@ class Plan:
                                   float(noise_floor))
         _lib.check(st, "cg_set_mlp")
 
+    def set_polish_iters(self, iters: int):
+        """LM iterations from the network's start point in the learned warm
+        start (default 2; 20, the cold start's cap, makes it a full fit)."""
+        _lib.check(self._lib.cg_set_polish_iters(self._h, int(iters)), "cg_set_polish_iters")
+
     def mlp_infer(self, y, out=None):
         nf = int(y.shape[0])
         yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")

@@ -153,3 +153,34 @@ def test_warm_path_with_trained_network():
     assert np.mean(st == 3) < 0.2
     # the gain over the method without the network: fewer LM iterations per frame
     assert warm["iters"].float().mean().item() < cold["iters"].float().mean().item()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not built")
+def test_warm_path_polish_to_convergence():
+    """With the polish run to the cold start's cap the warm form is a full LM
+    fit from the network's start point: parity with the oracle's warm form at
+    the same setting, and out-of-range settings are refused."""
+    d = np.load(WEIGHTS)
+    spec = synth.spec_learned()
+    bt = synth.make_batch(spec, 1024, seed=9)
+    ref = oracle.reference_spectrum(bt.ref_frames, spec.bins).astype(np.float32)
+    ora = oracle.pipeline.process_batch_warm(bt.frames, spec.bins, ref,
+                                             d["params"].astype(np.float64), d["out_mean"],
+                                             d["out_std"], float(d["noise_floor"]),
+                                             polish_iter=20)
+    plan = cg.Plan(spec.n, spec.fs, spec.bins, ref)
+    plan.set_mlp(d["params"], d["out_mean"], d["out_std"], float(d["noise_floor"]))
+    for bad in (0, -1, 65):
+        with pytest.raises(cg.CombGpuError):
+            plan.set_polish_iters(bad)
+    plan.set_polish_iters(20)
+    fr = torch.from_numpy(bt.frames).to(DEV)
+    warm = plan.process(fr, flags=cg.FIT_WARM_MLP, want=("params", "status", "iters"))
+    torch.cuda.synchronize()
+    st = warm["status"].cpu().numpy()
+    res = centre_parity(ora["y"], warm["params"].cpu().numpy(), ora["params"],
+                        np.where(ora["status"] == 3, 0, ora["status"]), ora["chi2"])
+    _say(f"polish 20: fallback {np.mean(st == 3):.4f} (oracle {np.mean(ora['status'] == 3):.4f}),"
+         f" parity {res['fraction']:.5f}, iters {warm['iters'].float().mean().item():.2f}")
+    assert res["fraction"] >= PASS_FRACTION, res
+    assert np.mean(st == ora["status"]) >= 0.99
