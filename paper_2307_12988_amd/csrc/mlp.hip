@@ -16,7 +16,7 @@
 //   GELU backward (dH = dA * GELU'(H), FP32 and bf16 copies).
 // * column sums (bias gradients), loss + dOut, Adam, bf16 weight refresh, a
 //   row gather for mini-batches.
-// * mlp_infer_kernel: the whole forward pass for 32 frames per block with the
+// * mlp_infer_kernel: the whole forward pass for 64 frames per block with the
 //   activations in LDS (never in HBM), input resampled to 220 points when
 //   K != 220, output de-standardised and rescaled to the tooth axis.
 #include <cmath>
@@ -247,18 +247,86 @@ __global__ void gather_kernel(const float* __restrict__ x, const float* __restri
 }
 
 // ---------------------------------------------------------------------------
-// fused inference: 32 frames per block, activations in LDS
-constexpr int IB = 32;            // frames per block
-constexpr int XP = MLP_IN_PAD + 8;   // LDS pitch of the input (232)
+// GELU for inference.  erf from Abramowitz & Stegun 7.1.26 (Hastings): with
+// t = 1 / (1 + p |x|), erf|x| = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5))))
+// exp(-x^2), absolute error at most 1.5e-7 -- far below the bf16 rounding
+// the activations get next, and a third of the instructions of erff.
+__device__ __forceinline__ float gelu_fast(float z) {
+  const float x = z * kInvSqrt2;
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  float poly = fmaf(t, 1.061405429f, -1.453152027f);
+  poly = fmaf(t, poly, 1.421413741f);
+  poly = fmaf(t, poly, -0.284496736f);
+  poly = fmaf(t, poly, 0.254829592f);
+  poly *= t;
+  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * ax * ax);  // exp(-x^2)
+  const float erf_abs = fmaf(-poly, e, 1.0f);
+  const float erf_x = __builtin_copysignf(erf_abs, x);
+  const float h = 0.5f * z;
+  return fmaf(h, erf_x, h);
+}
+
+// fused inference: 64 frames per block, activations in LDS
+constexpr int IB = 64;               // frames per block
 constexpr int HP = MLP_HID + 8;      // LDS pitch of hidden activations (264)
 
-__global__ __launch_bounds__(256) void mlp_infer_kernel(
+// One dense layer + bias + GELU for the block's 64 frames: wave w computes all
+// 64 rows of hidden units 64 w .. 64 w + 63 (4 x 4 tiles of 16 x 16).  The
+// weight fragments stream from L2 (each block reads every weight once).
+template <int KDIM>
+__device__ __forceinline__ void dense_gelu64(const uint16_t* in, int pitch,
+                                             const uint16_t* __restrict__ w,
+                                             const float* __restrict__ bias, uint16_t* outb,
+                                             int wave, int lane) {
+  const int fr = lane & 15, kq = (lane >> 4) * 8;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* wrow = w + (size_t)(wave * 64 + fr) * KDIM + kq;
+#pragma unroll
+  for (int k0 = 0; k0 < KDIM; k0 += 32) {
+    u16x8 wf[4], af[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      wf[j] = *reinterpret_cast<const u16x8*>(wrow + (size_t)j * 16 * KDIM + k0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      af[i] = *reinterpret_cast<const u16x8*>(in + (i * 16 + fr) * pitch + k0 + kq);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i]),
+                                                            __builtin_bit_cast(bf16x8, wf[j]),
+                                                            acc[i][j], 0, 0, 0);
+  }
+  __syncthreads();  // every wave has read `in` before `outb` (may alias) is written
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = wave * 64 + j * 16 + fr;
+    const float bn = bias[n];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = i * 16 + (lane >> 4) * 4 + e;
+        outb[r * HP + n] = to_bf16(gelu_fast(acc[i][j][e] + bn));
+      }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void mlp_infer_kernel(
     const float* __restrict__ y, int64_t nf, int k, const uint16_t* __restrict__ w1,
     const float* __restrict__ b1, const uint16_t* __restrict__ w2, const float* __restrict__ b2,
     const uint16_t* __restrict__ w3, const float* __restrict__ b3, MlpScale sc,
     float* __restrict__ p0, const int32_t* __restrict__ dev_n) {
+  // one activation buffer: each layer reads all of it before the barrier in
+  // dense_gelu64 and overwrites it after (34 KB: four blocks fit on a CU)
   __shared__ __attribute__((aligned(16))) uint16_t s_x[IB * HP];
-  __shared__ __attribute__((aligned(16))) uint16_t s_h[IB * HP];
   __shared__ float s_out[IB * 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t f0 = (int64_t)blockIdx.x * IB;
@@ -287,73 +355,28 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(
         v = y[f * k + lo] * (1.f - t) + y[f * k + hi] * t;
       }
     }
-    s_x[r * XP + j] = to_bf16(v);
+    s_x[r * HP + j] = to_bf16(v);
   }
   __syncthreads();
-  // layers 1 and 2: each wave computes 32 rows x 64 hidden units
-  auto dense_gelu = [&](const uint16_t* in, int pitch, int kdim, const uint16_t* w, int ldw,
-                        const float* bias, uint16_t* outb) {
-    f32x4 acc[2][4];
+  dense_gelu64<MLP_IN_PAD>(s_x, HP, w1, b1, s_x, wave, lane);
+  dense_gelu64<MLP_HID>(s_x, HP, w2, b2, s_x, wave, lane);
+  // layer 3 (256 -> 4, padded to one 16-column tile): wave w takes rows 16 w .. 16 w + 15
+  {
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < kdim; k0 += 32) {
-      u16x8 af[2], wf[4];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        af[i] = *reinterpret_cast<const u16x8*>(in + (i * 16 + fr) * pitch + k0 + kq);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int n = wave * 64 + j * 16 + fr;
-        wf[j] = *reinterpret_cast<const u16x8*>(w + (size_t)n * ldw + k0 + kq);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf16x8, af[i]), __builtin_bit_cast(bf16x8, wf[j]), acc[i][j],
-              0, 0, 0);
-    }
-    __syncthreads();  // every wave has read `in` before `outb` (may alias) is written
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int n = wave * 64 + j * 16 + fr;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = i * 16 + (lane >> 4) * 4 + e;
-          outb[r * HP + n] = to_bf16(gelu(acc[i][j][e] + bias[n]));
-        }
-      }
-    __syncthreads();
-  };
-  dense_gelu(s_x, XP, MLP_IN_PAD, w1, MLP_IN_PAD, b1, s_h);
-  dense_gelu(s_h, HP, MLP_HID, w2, MLP_HID, b2, s_x);
-  // layer 3 (256 -> 4, padded to one 16-column tile): wave 0
-  if (wave == 0) {
-    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
     for (int k0 = 0; k0 < MLP_HID; k0 += 32) {
       const u16x8 wf = *reinterpret_cast<const u16x8*>(w3 + (size_t)fr * MLP_HID + k0 + kq);
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const u16x8 af = *reinterpret_cast<const u16x8*>(s_x + (i * 16 + fr) * HP + k0 + kq);
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af),
-                                                         __builtin_bit_cast(bf16x8, wf), acc[i],
-                                                         0, 0, 0);
-      }
+      const u16x8 af = *reinterpret_cast<const u16x8*>(s_x + (wave * 16 + fr) * HP + k0 + kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af),
+                                                    __builtin_bit_cast(bf16x8, wf), acc, 0, 0, 0);
     }
     if (fr < 4) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) s_out[(i * 16 + (lane >> 4) * 4 + e) * 4 + fr] = acc[i][e] + b3[fr];
+      for (int e = 0; e < 4; ++e) s_out[(wave * 16 + (lane >> 4) * 4 + e) * 4 + fr] = acc[e] + b3[fr];
     }
   }
   __syncthreads();
-  if (tid < IB * 4) {
+  {
     const int r = tid >> 2, j = tid & 3;
     const int64_t f = f0 + r;
     if (f < nf) {
