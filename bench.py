@@ -42,9 +42,15 @@ MEDIAN_OPS_PER_OUTPUT = 32 + 340 / 2 + 14
 SEED = 1
 
 # HBM bytes per launch of the paper-rate workload from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled x2 and x1 by a 1 GiB copy), valid only for the kernel
-# source they were taken on: kernel -> (source, sha256 prefix, read B, write B)
-TRAFFIC = {}
+# WRITE_SIZE (KiB per dispatch, scaled x2 and x1 by a 1 GiB copy), valid only
+# for the kernel sources they were taken on:
+# kernel -> (sources, sha256 prefix of their concatenation, read B, write B)
+TRAFFIC = {
+    "fft_teeth": (("fft_teeth.hip",), "409172e6710de519", 131285.6 * 2 * 1024, 56320.0 * 1024),
+    "median_start": (("median.hip", "wave.h"), "e2f33ebc08e1deb2", 39080.4 * 2 * 1024,
+                     1024.0 * 1024),
+    "lm_fit": (("lm.hip", "wave.h"), "0ce4f66ab3093d44", 28738.5 * 2 * 1024, 1792.1 * 1024),
+}
 
 
 def traffic_bytes(kernel):
@@ -52,12 +58,14 @@ def traffic_bytes(kernel):
     if not ent:
         return None
     import hashlib
-    src = os.path.join(ROOT, "paper_2307_12988_amd", "csrc", ent[0])
+    h = hashlib.sha256()
     try:
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        for name in ent[0]:
+            with open(os.path.join(ROOT, "paper_2307_12988_amd", "csrc", name), "rb") as f:
+                h.update(f.read())
     except OSError:
         return None
-    return ent[2] + ent[3] if digest == ent[1] else None
+    return ent[2] + ent[3] if h.hexdigest()[:16] == ent[1] else None
 
 
 def _log(msg):
