@@ -36,9 +36,12 @@ HBM_PEAK_GBS = 8000.0
 VALU_FP32_PEAK_TFLOPS = 78.6
 # single-operand-rate VALU instructions (min/max): 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
 VALU_OPS_PEAK_TOPS = 39.3
-# min/max operations per filtered value: one 7-value row sort (16 compare-
-# exchanges) plus half of the shared 6-row merge (340) and one final merge (14)
-MEDIAN_OPS_PER_OUTPUT = 32 + 340 / 2 + 14
+# min/max operations per filtered value: four windows per step share merged
+# row pairs (4 row sorts of 16 compare-exchanges, 2 pair merges of 42, a
+# 100-op common merge, 2 x 72 shared-set merges, 4 x 14 final merges per four
+# values: 128), plus each 16-frame block's start-up (6 row sorts and 2 pair
+# merges: 276 per 16 values)
+MEDIAN_OPS_PER_OUTPUT = 128 + 276 / 16
 SEED = 1
 
 # HBM bytes per launch of the paper-rate workload from rocprofv3 FETCH_SIZE and

@@ -3,24 +3,33 @@
 Build step (run by paper_2307_12988_amd/build.py; output median49_net.inc).
 
 The median of a 7x7 window is the 25th smallest of its 49 values.  The kernel
-sorts each 7-value row segment of the window once (shared by the seven windows
-that contain it) and keeps the last rows in registers while it walks down the
-frames.  Two vertically adjacent windows share six rows, so for each pair:
+sorts each 7-value row segment of the image once and walks down the frames
+computing four vertically adjacent windows at a time, W0..W3 over rows
+t..t+6, t+1..t+7, t+2..t+8 and t+3..t+9.  With L1..L4 the merged row pairs
+(t+1, t+2), (t+3, t+4), (t+5, t+6), (t+7, t+8):
 
-* CG_MERGE6_R17_24 merges the six shared sorted rows (42 values) and keeps
-  only their ranks 17..24: at most 7 values of the remaining row can fall
-  below or above, so the 17 smallest lie below the median and the 17 largest
-  above it, and the median is the 8th smallest of those 8 values together
-  with the remaining row;
-* CG_MERGE8_7_R7 merges those 8 values with one sorted row and returns the
-  8th smallest, once for each window of the pair.
+* W0 and W1 share the 42 values of L1, L2, L3; W2 and W3 those of L2, L3, L4.
+  At most 7 values of a window's own row can fall below or above, so only
+  ranks 17..24 of a shared set can be the median: the median is the 8th
+  smallest of those 8 values together with the own row (CG_MERGE8_7_R7).
+* L2 and L3 (28 values) are common to both shared sets.  A shared set adds 14
+  values (L1 or L4) to them, so its ranks 17..24 only need ranks 3..24 of
+  the common part (CG_CORE_R3_24): the 3 smallest dropped values lie at rank
+  <= 16 of the shared set and the 3 largest at rank >= 25.  Ranks 17..24 of
+  the shared set are then ranks 14..21 of those 22 values merged with L1 or
+  L4 (CG_PAIR_R14_21).
+* L3 and L4 of one step are L1 and L2 of the next (t + 4), so each step merges
+  two new row pairs (CG_MERGE77) and sorts four new rows.
 
-Both are Batcher odd-even merges (lists padded to 8 with +inf) pruned
-symbolically to the outputs needed; comparisons against a constant +inf
-vanish and only the min or max side of a comparator that is used is emitted.
-CG_SORT7 is the 16-comparator 7-input sorting network.  The script checks the
-composed networks against numpy's median on random inputs with ties before
-writing the file.
+Per output that is 4 x 32 (row sorts) + 2 x 42 + 100 + 2 x 72 + 4 x 14 = 512
+min/max operations per four outputs, 128 per output.
+
+All merges are Batcher odd-even merges (lists padded to a power of two with
++inf) pruned symbolically to the outputs needed; comparisons against a
+constant +inf vanish and only the min or max side of a comparator that is
+used is emitted.  CG_SORT7 is the 16-comparator 7-input sorting network.  The
+script checks the composed networks against numpy's median on random inputs
+with ties before writing the file.
 """
 
 import os
@@ -63,10 +72,11 @@ def merge_select(list_lens, want_ranks):
     while n_lists < len(list_lens):
         n_lists *= 2
     per = 8
+    while per < max(list_lens):
+        per *= 2
     wires = [INF] * (n_lists * per)
     base = 0
     for li, ln in enumerate(list_lens):
-        assert ln <= per
         for r in range(ln):
             wires[li * per + r] = base + r
         base += ln
@@ -136,19 +146,29 @@ def emit_sort7(name):
 
 def main(path):
     _check_sort7()
-    k6, o6 = merge_select([7] * 6, list(range(17, 25)))
+    k77, o77 = merge_select([7, 7], list(range(14)))
+    kc, oc = merge_select([14, 14], list(range(3, 25)))
+    kp, op = merge_select([22, 14], list(range(14, 22)))
     kf, of = merge_select([8, 7], [7])
     rng = np.random.default_rng(0)
     for trial in range(4):
-        v = rng.random((20000, 49)) if trial % 2 == 0 else \
-            rng.integers(0, 5, size=(20000, 49)).astype(np.float64)
-        v = np.sort(v.reshape(-1, 7, 7), axis=2).reshape(-1, 49)
-        a = evaluate(k6, o6, v[:, :42])
-        got = evaluate(kf, of, np.concatenate([a, v[:, 42:]], axis=1))[:, 0]
-        assert np.array_equal(got, np.sort(v, axis=1)[:, 24])
+        v = rng.random((20000, 70)) if trial % 2 == 0 else \
+            rng.integers(0, 5, size=(20000, 70)).astype(np.float64)
+        rows = np.sort(v.reshape(-1, 10, 7), axis=2)  # rows t .. t+9, each sorted
+        lists = [evaluate(k77, o77, np.concatenate([rows[:, 2 * j + 1], rows[:, 2 * j + 2]],
+                                                   axis=1)) for j in range(4)]
+        core = evaluate(kc, oc, np.concatenate([lists[1], lists[2]], axis=1))
+        sa = evaluate(kp, op, np.concatenate([core, lists[0]], axis=1))
+        sb = evaluate(kp, op, np.concatenate([core, lists[3]], axis=1))
+        for w, (shared, own) in enumerate([(sa, 0), (sa, 7), (sb, 2), (sb, 9)]):
+            got = evaluate(kf, of, np.concatenate([shared, rows[:, own]], axis=1))[:, 0]
+            want = np.sort(v.reshape(-1, 10, 7)[:, w:w + 7].reshape(-1, 49), axis=1)[:, 24]
+            assert np.array_equal(got, want), (trial, w)
     text = ["// Generated by gen_median_net.py -- do not edit.", ""]
     text.append(emit_sort7("CG_SORT7"))
-    text.append(emit("CG_MERGE6_R17_24", k6, o6, 42))
+    text.append(emit("CG_MERGE77", k77, o77, 14))
+    text.append(emit("CG_CORE_R3_24", kc, oc, 28))
+    text.append(emit("CG_PAIR_R14_21", kp, op, 36))
     text.append(emit("CG_MERGE8_7_R7", kf, of, 15))
     with open(path, "w") as fh:
         fh.write("\n".join(text))
