@@ -429,6 +429,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--pool", type=int, default=4, help="distinct batches resident in HBM")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="paper-rate: HIP streams that consecutive batches alternate over")
     ap.add_argument("--frames", type=int, default=65536)
     ap.add_argument("--cpu-frames", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -485,14 +487,23 @@ def main():
     ref = plan.reference_from_frames(ref_frames).cpu().numpy()
     plan.set_reference(ref)
 
-    ws = torch.empty(plan.workspace_bytes(nf), dtype=torch.uint8, device=dev)
-    params = torch.empty((nf, 4), dtype=torch.float32, device=dev)
-    iters = torch.empty((nf,), dtype=torch.int32, device=dev)
-    status = torch.empty((nf,), dtype=torch.int32, device=dev)
+    # batches are independent: with --streams S > 1, consecutive batches go to
+    # S HIP streams (default priority) with their own workspace and outputs, so
+    # one batch's kernels can overlap the next one's
+    ns = max(1, args.streams)
+    streams = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(dev) for _ in range(ns - 1)]
+    wss = [torch.empty(plan.workspace_bytes(nf), dtype=torch.uint8, device=dev) for _ in range(ns)]
+    outs = [(torch.empty((nf, 4), dtype=torch.float32, device=dev),
+             torch.empty((nf,), dtype=torch.int32, device=dev),
+             torch.empty((nf,), dtype=torch.int32, device=dev)) for _ in range(ns)]
+    ws = wss[0]
+    params, iters, status = outs[0]
 
     def step(i):
-        plan.process(pool[i % len(pool)], params=params, iters=iters, status=status,
-                     workspace=ws, want=())
+        j = i % ns
+        with torch.cuda.stream(streams[j]):
+            plan.process(pool[i % len(pool)], params=outs[j][0], iters=outs[j][1],
+                         status=outs[j][2], workspace=wss[j], want=())
 
     _log("warmup ...")
     for i in range(args.warmup):
@@ -508,7 +519,9 @@ def main():
     gbs = nf * n * 2 * args.steps / wall / 1e9
     sps = nf * args.steps / wall
 
-    # fit statistics of the last step's batch
+    # fit statistics of a batch processed on the first stream
+    step(0)
+    torch.cuda.synchronize(dev)
     it_np = iters.cpu().numpy()
     st_np = status.cpu().numpy()
 
@@ -589,7 +602,7 @@ def main():
         "config": {"workload": f"paper-rate comb stream: {nf} frames x {n} int16 samples per "
                                f"batch, {k} teeth, cold-start 7x7 median + LM (<=20 it)",
                    "frames_per_batch": nf, "frame_len": n, "n_teeth": k,
-                   "pool_batches": args.pool},
+                   "pool_batches": args.pool, "streams": ns},
         "spectra_per_s": sps,
         "fit": {"mean_iters": float(it_np.mean()), "converged_frac": float(np.mean(st_np == 0)),
                 "status_counts": np.bincount(st_np, minlength=4).tolist()},
