@@ -408,7 +408,8 @@ def multistream(args, torch, cg, dev):
         "data": "synthetic",
         "config": {"workload": f"{ns} interleaved streams, frame lengths 512-8192, 64-440 teeth, "
                                f"bursts of 256-4096 frames, learned warm start, ring pipeline",
-                   "streams": ns, "slots_per_stream": args.slots},
+                   "streams": ns, "slots_per_stream": args.slots,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "spectra_per_s": s1["frames_per_s"],
         "phase1_max_rate": {k: s1[k] for k in s1}, "phase1_ring_full_events": full,
         "phase2_paced": {"seconds": args.seconds, "offered_GBps": offered / 1e9,
@@ -444,16 +445,25 @@ def main():
     ap.add_argument("--phase1", type=float, default=5.0,
                     help="multistream: length of the maximum-rate phase")
     ap.add_argument("--slots", type=int, default=8, help="multistream: ring slots per stream")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="hardware queues per process (GPU_MAX_HW_QUEUES, 1..32; 0 = leave "
+                         "the environment as it is)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (reference for "
                          "the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: the hot path has no multi-GPU form in this "
-              "build (frames are independent; see the sharding note in DESIGN.md)",
+        print("bench.py runs on one GPU only: the hot path has no multi-GPU form (frames "
+              "are independent, so it would shard by frame ranges or whole streams)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.hw_queues:
+        if not 1 <= args.hw_queues <= 32:
+            print("--hw-queues must be in 1..32", file=sys.stderr)
+            sys.exit(2)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)  # read when HIP initialises
 
     import torch
 

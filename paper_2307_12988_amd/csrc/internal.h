@@ -79,8 +79,9 @@ hipError_t launch_start_points(const float* m, int64_t n_frames, int k, float* o
                                hipStream_t s);
 
 // A5: Levenberg-Marquardt from start points p0.  chunk = spectra per wave
-// (<= 0: chosen from n_frames).
-int lm_chunk(int64_t n_frames);
+// (<= 0: chosen from n_frames and the tooth count).
+int lm_group(int n_teeth);
+int lm_chunk(int64_t n_frames, int n_teeth);
 hipError_t launch_lm(const float* y, const float* p0, int64_t n_frames, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
                      int chunk = 0, const int32_t* dev_n = nullptr);

@@ -8,22 +8,23 @@
 //
 // gfx950 layout
 // -------------
-// A wavefront works on four spectra at a time, one per group of 16 lanes (one
-// DPP row); lane gl of a group owns teeth i = gl + 16 q.  Per evaluation each
-// lane computes model, residual and chi2 in FP64 (so the chi2 comparisons and
-// the 1e-6 relative-decrease test see the same values an FP64 reference sees)
-// and the four Jacobian columns and the 14 normal-equation products in FP32;
-// 16-lane DPP butterflies give every lane of the group bit-identical sums.  The
-// damped 4x4 system is solved per group by a Cholesky factorisation in FP64.
-// Evaluating a trial point also produces the normal equations there, so an
-// accepted step needs no second pass.
+// A wavefront works on 64/G spectra at a time, one per group of G lanes (G = 8
+// up to 224 teeth, else 16); lane gl of a group owns teeth i = gl + G q.  Per
+// evaluation each lane computes model, residual and chi2 in FP64 (so the chi2
+// comparisons and the 1e-6 relative-decrease test see the same values an
+// FP64 reference sees) and the four Jacobian columns and the 14
+// normal-equation products in FP32; DPP butterflies inside the group give
+// every lane of the group bit-identical sums.  The damped 4x4 system is solved
+// per group by a Cholesky factorisation in FP64.  Evaluating a trial point
+// also produces the normal equations there, so an accepted step needs no
+// second pass.
 //
 // A wave owns a contiguous chunk of spectra.  The LM loop body is the same for
 // every iteration, so groups run independent fits in lock step: when a group
 // finishes it writes its result and takes the next spectrum of the chunk (the
 // hand-out index is wave-uniform, advanced with a ballot), evaluates the new
 // start point in the next trip and carries on.  A wave exits when its chunk is
-// exhausted and all four groups are idle; every fit is bounded by max_iter.
+// exhausted and all its groups are idle; every fit is bounded by max_iter.
 //
 // Schedule (the paper fixes only the cap and the tolerance): lam0 = 1e-3,
 // /10 on accept, *10 on reject; accept when finite, width > 0 and chi2 does
@@ -68,8 +69,8 @@ __device__ __forceinline__ double rcp1_d(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
-// Sums over the group's teeth at one parameter point (Q = ceil(k / 16) slots
-// per lane).  The arithmetic is the same for every lane; teeth past the last
+// Sums over the group's teeth at one parameter point (a group of G lanes,
+// Q = ceil(k / G) slots per lane).  The arithmetic is the same for every lane; teeth past the last
 // one, which only the last slot can hold, contribute exact zeros, and a
 // group whose point is not used (idle, or a rejected trial point) simply
 // computes values nobody reads, so the loop body has no divergent branches.
@@ -79,10 +80,10 @@ __device__ __forceinline__ double rcp1_d(double x) {
 // D = 1 + u^2, s = d / D^2,
 //   df/dc = (-4 b / w) s u,   df/dw = (-2 b / w) s u^2,
 //   df/dd = (-b) / D,         df/db = 1 - d / D.
-template <int Q>
+template <int G, int Q>
 __device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, double c, double w,
                                          double d, double b, Sums& s) {
-  int gl = lane_id() & 15;
+  int gl = lane_id() & (G - 1);
   asm volatile("" : "+v"(gl));  // slot indices are rebuilt per call, not kept live
   float acc[14];
 #pragma unroll
@@ -96,7 +97,7 @@ __device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, double c, 
     // index passes through one before its arithmetic and its sums pass
     // through one after it.  Left alone, the compiler evaluates the FP64 part
     // of every slot first and keeps all of it live (about 100 extra VGPRs).
-    int i = gl + 16 * q;
+    int i = gl + G * q;
     asm volatile("" : "+v"(i));
     const double u = fma((double)i, two_iw, -c_iw);
     const double den = fma(u, u, 1.0);
@@ -140,7 +141,7 @@ __device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, double c, 
   }
   float sum[14];
 #pragma unroll
-  for (int j = 0; j < 14; ++j) sum[j] = sum16(acc[j]);
+  for (int j = 0; j < 14; ++j) sum[j] = sum_group<G>(acc[j]);
   // column factors: c, w, d carry al, be, ga; b carries 1
   const float bf = (float)b, two_iwf = (float)two_iw;
   const float al = -2.0f * bf * two_iwf, be = -bf * two_iwf, ga = -bf;
@@ -158,7 +159,7 @@ __device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, double c, 
   s.g[1] = sum[11] * be;
   s.g[2] = sum[12] * ga;
   s.g[3] = sum[13];
-  s.chi2 = sum16(chi2);
+  s.chi2 = sum_group<G>(chi2);
 }
 
 // Solve (A + lam diag A) delta = g by Cholesky in FP64; false if the damped
@@ -193,18 +194,18 @@ __device__ __forceinline__ bool damped_solve(const Sums& s, double lam, double (
          isfinite(delta[3]);
 }
 
-template <int Q>
+template <int G, int Q>
 __device__ __forceinline__ void load_spectrum(const float* __restrict__ y, int64_t s, int k,
                                               float (&yv)[Q]) {
-  const int gl = lane_id() & 15;
+  const int gl = lane_id() & (G - 1);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int i = gl + 16 * q;
+    const int i = gl + G * q;
     yv[q] = (q < Q - 1 || i < k) ? y[s * k + i] : 0.0f;  // only the last slot can be partial
   }
 }
 
-template <int Q>
+template <int G, int Q>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lm_kernel(const float* __restrict__ y,
                                                  const float* __restrict__ p0,
                                                  const int32_t* __restrict__ idx,
@@ -214,9 +215,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                                  int32_t* __restrict__ iters,
                                                  int32_t* __restrict__ status,
                                                  float* __restrict__ chi2_out, int status_code) {
+  constexpr int NG = 64 / G;  // spectra in flight per wave
   const int lane = lane_id();
-  const int grp = lane >> 4;
-  const int gl = lane & 15;
+  const int grp = lane / G;
+  const int gl = lane & (G - 1);
   const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t base = wave * chunk;
   int64_t n = nf;
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   const int64_t end = base + chunk < n ? base + chunk : n;
 
   int64_t s = base + grp;  // spectrum of this group (>= end: idle)
-  int64_t next = base + 4;  // wave-uniform hand-out index
+  int64_t next = base + NG;  // wave-uniform hand-out index
   bool active = s < end;
   bool fresh = true;
   float yv[Q];
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   Sums cur;
   if (active) {
     fi = idx ? (int64_t)idx[s] : s;
-    load_spectrum<Q>(y, fi, k, yv);
+    load_spectrum<G, Q>(y, fi, k, yv);
     c = p0[fi * 4 + 0];
     w = p0[fi * 4 + 1];
     d = p0[fi * 4 + 2];
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                     isfinite(tb) && tw > 0.0);
     // 2. evaluation (start point for fresh groups, trial point otherwise)
     Sums trial;
-    evaluate<Q>(yv, k, tc, tw, td, tb, trial);
+    evaluate<G, Q>(yv, k, tc, tw, td, tb, trial);
     // 3. decisions, as selects: the four groups of a wave are in different
     //    states, and branches here would only execute every path with copies
     const bool start = active && fresh;
@@ -304,13 +306,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     const uint64_t fin = __ballot(done && gl == 0);
     if (fin != 0ull) {
       if (done) {
-        const uint64_t below = fin & ((1ull << (grp * 16)) - 1ull);
+        const uint64_t below = fin & ((1ull << (grp * G)) - 1ull);
         s = next + __popcll(below);
         active = s < end;
         fresh = true;
         if (active) {
           fi = idx ? (int64_t)idx[s] : s;
-          load_spectrum<Q>(y, fi, k, yv);
+          load_spectrum<G, Q>(y, fi, k, yv);
           c = p0[fi * 4 + 0];
           w = p0[fi * 4 + 1];
           d = p0[fi * 4 + 2];
@@ -356,76 +358,92 @@ hipError_t launch_fallback_select(const float* chi2, int64_t nf, int k, float no
   return hipGetLastError();
 }
 
-int lm_chunk(int64_t nf) {
-  // spectra per wave: enough waves to fill 256 CUs several times over, and at
-  // least a few spectra per group so finished groups have work to take
-  int64_t c = (nf + 8191) / 8192;
-  c = ((c + 3) / 4) * 4;
-  if (c < 4) c = 4;
-  if (c > 64) c = 64;
+// Lanes per spectrum: groups of 8 (eight spectra per wave) while the slots
+// per lane stay within 28 (K <= 224), else groups of 16.  Wider waves amortise
+// the solve and the decisions over more spectra and shorten the reductions.
+int lm_group(int k) { return k <= 224 ? 8 : 16; }
+
+int lm_chunk(int64_t nf, int k) {
+  // spectra per wave: about four per group, so a group that finishes early
+  // has work to take, while keeping at least 2048 waves (two per SIMD) when
+  // the batch allows it
+  const int ng = 64 / lm_group(k);
+  int64_t c = nf / 2048;
+  if (c > 4 * ng) c = 4 * ng;
+  c = (c / ng) * ng;
+  if (c < ng) c = ng;
   return (int)c;
 }
 
-// The fit kernel is instantiated for every slot count Q = ceil(k / 16), so
-// only its last slot needs masking.
-#define CG_LM_SWITCH(k, CALL)                                                            \
-  switch (((k) + 15) / 16) {                                                             \
-    case 1: { constexpr int Q = 1; CALL; } break;                                        \
-    case 2: { constexpr int Q = 2; CALL; } break;                                        \
-    case 3: { constexpr int Q = 3; CALL; } break;                                        \
-    case 4: { constexpr int Q = 4; CALL; } break;                                        \
-    case 5: { constexpr int Q = 5; CALL; } break;                                        \
-    case 6: { constexpr int Q = 6; CALL; } break;                                        \
-    case 7: { constexpr int Q = 7; CALL; } break;                                        \
-    case 8: { constexpr int Q = 8; CALL; } break;                                        \
-    case 9: { constexpr int Q = 9; CALL; } break;                                        \
-    case 10: { constexpr int Q = 10; CALL; } break;                                      \
-    case 11: { constexpr int Q = 11; CALL; } break;                                      \
-    case 12: { constexpr int Q = 12; CALL; } break;                                      \
-    case 13: { constexpr int Q = 13; CALL; } break;                                      \
-    case 14: { constexpr int Q = 14; CALL; } break;                                      \
-    case 15: { constexpr int Q = 15; CALL; } break;                                      \
-    case 16: { constexpr int Q = 16; CALL; } break;                                      \
-    case 17: { constexpr int Q = 17; CALL; } break;                                      \
-    case 18: { constexpr int Q = 18; CALL; } break;                                      \
-    case 19: { constexpr int Q = 19; CALL; } break;                                      \
-    case 20: { constexpr int Q = 20; CALL; } break;                                      \
-    case 21: { constexpr int Q = 21; CALL; } break;                                      \
-    case 22: { constexpr int Q = 22; CALL; } break;                                      \
-    case 23: { constexpr int Q = 23; CALL; } break;                                      \
-    case 24: { constexpr int Q = 24; CALL; } break;                                      \
-    case 25: { constexpr int Q = 25; CALL; } break;                                      \
-    case 26: { constexpr int Q = 26; CALL; } break;                                      \
-    case 27: { constexpr int Q = 27; CALL; } break;                                      \
-    case 28: { constexpr int Q = 28; CALL; } break;                                      \
-    default: return hipErrorInvalidValue;                                                \
+namespace {
+
+template <int G, int Q>
+hipError_t launch_lm_gq(const float* y, const float* p0, const int32_t* idx,
+                        const int32_t* count, int64_t nf, int k, int max_iter, int chunk,
+                        float* params, int32_t* iters, int32_t* status, float* chi2,
+                        int32_t status_code, hipStream_t s) {
+  const int64_t waves = (nf + chunk - 1) / chunk;
+  const int64_t blocks = (waves + 3) / 4;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((lm_kernel<G, Q>), dim3((unsigned)blocks), dim3(256), 0, s, y, p0, idx,
+                     count, nf, k, max_iter, chunk, params, iters, status, chi2, status_code);
+  return hipGetLastError();
+}
+
+// The fit kernel is instantiated for every slot count Q = ceil(k / G) <= 28,
+// so only its last slot needs masking.
+template <int G>
+hipError_t launch_lm_g(const float* y, const float* p0, const int32_t* idx,
+                       const int32_t* count, int64_t nf, int k, int max_iter, int chunk,
+                       float* params, int32_t* iters, int32_t* status, float* chi2,
+                       int32_t status_code, hipStream_t s) {
+#define CG_LM_CASE(QV)                                                                   \
+  case QV:                                                                               \
+    return launch_lm_gq<G, QV>(y, p0, idx, count, nf, k, max_iter, chunk, params, iters, \
+                               status, chi2, status_code, s);
+  switch ((k + G - 1) / G) {
+    CG_LM_CASE(1) CG_LM_CASE(2) CG_LM_CASE(3) CG_LM_CASE(4) CG_LM_CASE(5) CG_LM_CASE(6)
+    CG_LM_CASE(7) CG_LM_CASE(8) CG_LM_CASE(9) CG_LM_CASE(10) CG_LM_CASE(11) CG_LM_CASE(12)
+    CG_LM_CASE(13) CG_LM_CASE(14) CG_LM_CASE(15) CG_LM_CASE(16) CG_LM_CASE(17)
+    CG_LM_CASE(18) CG_LM_CASE(19) CG_LM_CASE(20) CG_LM_CASE(21) CG_LM_CASE(22)
+    CG_LM_CASE(23) CG_LM_CASE(24) CG_LM_CASE(25) CG_LM_CASE(26) CG_LM_CASE(27)
+    CG_LM_CASE(28)
+    default:
+      return hipErrorInvalidValue;
   }
+#undef CG_LM_CASE
+}
+
+hipError_t launch_lm_any(const float* y, const float* p0, const int32_t* idx,
+                         const int32_t* count, int64_t nf, int k, int max_iter, int chunk,
+                         float* params, int32_t* iters, int32_t* status, float* chi2,
+                         int32_t status_code, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  if (lm_group(k) == 8)
+    return launch_lm_g<8>(y, p0, idx, count, nf, k, max_iter, chunk, params, iters, status,
+                          chi2, status_code, s);
+  return launch_lm_g<16>(y, p0, idx, count, nf, k, max_iter, chunk, params, iters, status,
+                         chi2, status_code, s);
+}
+
+}  // namespace
 
 hipError_t launch_lm(const float* y, const float* p0, int64_t nf, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
                      int chunk, const int32_t* dev_n) {
-  if (chunk <= 0) chunk = lm_chunk(nf);
-  const int64_t waves = (nf + chunk - 1) / chunk;
-  const int64_t blocks = (waves + 3) / 4;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  CG_LM_SWITCH(k, hipLaunchKernelGGL(lm_kernel<Q>, dim3((unsigned)blocks), dim3(256), 0, s, y,
-                                        p0, nullptr, dev_n, nf, k, max_iter, chunk, params,
-                                        iters, status, chi2, -1));
-  return hipGetLastError();
+  if (chunk <= 0) chunk = lm_chunk(nf, k);
+  return launch_lm_any(y, p0, nullptr, dev_n, nf, k, max_iter, chunk, params, iters, status,
+                       chi2, -1, s);
 }
 
 hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx,
                              const int32_t* count, int64_t n_cap, int k, int max_iter,
                              float* params, int32_t* iters, int32_t* status, float* chi2,
                              int32_t status_code, hipStream_t s) {
-  const int chunk = 4;  // the count is only known on the device: small chunks keep waves busy
-  const int64_t waves = (n_cap + chunk - 1) / chunk;
-  const int64_t blocks = (waves + 3) / 4;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  CG_LM_SWITCH(k, hipLaunchKernelGGL(lm_kernel<Q>, dim3((unsigned)blocks), dim3(256), 0, s, y,
-                                        p0, idx, count, n_cap, k, max_iter, chunk, params, iters,
-                                        status, chi2, status_code));
-  return hipGetLastError();
+  // the count is only known on the device: one spectrum per group keeps waves busy
+  const int chunk = 64 / lm_group(k);
+  return launch_lm_any(y, p0, idx, count, n_cap, k, max_iter, chunk, params, iters, status,
+                       chi2, status_code, s);
 }
 
 }  // namespace cg

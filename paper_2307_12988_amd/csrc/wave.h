@@ -55,6 +55,32 @@ __device__ __forceinline__ int sum16(int v) {
   v += dpp_i<0x140>(v);
   return v;
 }
+// Sums over groups of 8 lanes (half rows): the two quad steps and the
+// half-row mirror.
+__device__ __forceinline__ float sum8(float v) {
+  v += dpp_f<0xB1>(v);
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  return v;
+}
+__device__ __forceinline__ double sum8(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  return v;
+}
+// Sum over a group of G lanes (G = 8 or 16), bit-identical in every lane.
+template <int G>
+__device__ __forceinline__ float sum_group(float v) {
+  if constexpr (G == 8) return sum8(v);
+  else return sum16(v);
+}
+template <int G>
+__device__ __forceinline__ double sum_group(double v) {
+  if constexpr (G == 8) return sum8(v);
+  else return sum16(v);
+}
+
 __device__ __forceinline__ uint64_t min16(uint64_t v) {
 #define CG_MIN_STEP(C)                                                                 \
   {                                                                                    \
