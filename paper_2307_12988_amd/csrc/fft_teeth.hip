@@ -15,9 +15,9 @@
 // * Stockham autosort passes, 16 points per thread held in registers: two
 //   radix-16 passes and one radix-M/256 pass (M = 256 .. 4096), so each frame
 //   makes two or three LDS exchanges.  Threads per frame T = M/16; a 256-thread
-//   workgroup holds 256/T frames.  LDS is split into real and imaginary
-//   planes with one padding word per 16 so the strided pass-1 stores are
-//   bank-conflict free.
+//   workgroup holds 256/T frames.  LDS holds interleaved complex points
+//   (one 64-bit access per point) with one padding point per 16 so the
+//   strided pass-1 stores are bank-conflict free.
 // * Twiddles come from a table of W_N^e built on the host in FP64 and rounded
 //   once to FP32 (no fast-math sin/cos on the device).
 // * Persistent blocks: the grid is sized to what fits on the chip, each block
@@ -29,7 +29,7 @@
 namespace cg {
 namespace {
 
-struct c32 {
+struct __attribute__((aligned(8))) c32 {
   float x, y;
 };
 
@@ -135,10 +135,10 @@ struct FftShape {
   static constexpr int PM = M + M / 16;     // padded plane length
   static constexpr int R3 = M / 256;        // radix of the last pass (1 = none)
   static constexpr int NB3 = R3 > 1 ? 16 / R3 : 0;  // last-pass butterflies per thread
-  static constexpr size_t PLANE_BYTES = sizeof(float) * 2 * FPB * PM;
+  static constexpr size_t PLANE_BYTES = sizeof(float) * 2 * FPB * PM;  // complex points
 };
 
-// Dynamic LDS: the real and imaginary planes of FPB frames, then one float4
+// Dynamic LDS: the complex points of FPB frames, then one float4
 // per tooth {packed padded LDS offsets of Z[k] and Z[M-k], Re W_N^k, Im W_N^k,
 // 0.5 / ref}.
 template <int LOGM>
@@ -163,9 +163,8 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
   constexpr int M = S::M, T = S::T, FPB = S::FPB, PM = S::PM, R3 = S::R3, NB3 = S::NB3;
   constexpr int N = 2 * M;
   extern __shared__ float4 lds4[];
-  float* s_re = reinterpret_cast<float*>(lds4);
-  float* s_im = s_re + FPB * PM;
-  float4* s_tooth = reinterpret_cast<float4*>(s_re + 2 * FPB * PM);
+  c32* s_c = reinterpret_cast<c32*>(lds4);  // FPB frames x PM complex points
+  float4* s_tooth = reinterpret_cast<float4*>(s_c + FPB * PM);
 
   if (dev_n) {
     const int64_t dn = *dev_n;
@@ -178,8 +177,7 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
   const int tid = threadIdx.x;
   const int fl = tid / T;
   const int j = tid - fl * T;
-  float* re = s_re + fl * PM;
-  float* im = s_im + fl * PM;
+  c32* zc = s_c + fl * PM;
 
   // per-tooth constants
   for (int i = tid; i < k_teeth; i += 256) {
@@ -237,39 +235,27 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 
     // ---- pass 1: radix 16, Ns = 1 ----
     dft16(v);
-    __syncthreads();  // the previous group's epilogue has read the planes
+    __syncthreads();  // the previous group's epilogue has read the points
     {
-      float* wr = re + 17 * j;  // padx(16 j + r) = 17 j + r
-      float* wi = im + 17 * j;
+      c32* w = zc + 17 * j;  // padx(16 j + r) = 17 j + r
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        wr[r] = v[r].x;
-        wi[r] = v[r].y;
-      }
+      for (int r = 0; r < 16; ++r) w[r] = v[r];
     }
     __syncthreads();
     // ---- pass 2: radix 16, Ns = 16 ----
     {
       constexpr int S2 = T + T / 16;
-      const float* rr = re + j + (j >> 4);
-      const float* ri = im + j + (j >> 4);
+      const c32* rd = zc + j + (j >> 4);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        v[r].x = rr[r * S2];
-        v[r].y = ri[r * S2];
-      }
+      for (int r = 0; r < 16; ++r) v[r] = rd[r * S2];
       __syncthreads();
 #pragma unroll
       for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w2[r - 1]);
       dft16(v);
       const int base = (j >> 4) * 256 + jm;
-      float* wr = re + base + (base >> 4);
-      float* wi = im + base + (base >> 4);
+      c32* w = zc + base + (base >> 4);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        wr[17 * r] = v[r].x;
-        wi[17 * r] = v[r].y;
-      }
+      for (int r = 0; r < 16; ++r) w[17 * r] = v[r];
     }
     __syncthreads();
     // ---- pass 3: radix M/256, Ns = 256 ----
@@ -277,13 +263,9 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 #pragma unroll
       for (int q = 0; q < NB3; ++q) {
         const int jp = j + T * q;
-        const float* rr = re + jp + (jp >> 4);
-        const float* ri = im + jp + (jp >> 4);
+        const c32* rd = zc + jp + (jp >> 4);
 #pragma unroll
-        for (int r = 0; r < R3; ++r) {
-          v[q * R3 + r].x = rr[272 * r];
-          v[q * R3 + r].y = ri[272 * r];
-        }
+        for (int r = 0; r < R3; ++r) v[q * R3 + r] = rd[272 * r];
       }
       __syncthreads();
 #pragma unroll
@@ -292,13 +274,9 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 #pragma unroll
         for (int r = 1; r < R3; ++r) v[q * R3 + r] = cmul(v[q * R3 + r], w3[q * (R3 - 1) + r - 1]);
         dft_r<R3>(v + q * R3);
-        float* wr = re + jp + (jp >> 4);
-        float* wi = im + jp + (jp >> 4);
+        c32* w = zc + jp + (jp >> 4);
 #pragma unroll
-        for (int r = 0; r < R3; ++r) {
-          wr[272 * r] = v[q * R3 + r].x;
-          wi[272 * r] = v[q * R3 + r].y;
-        }
+        for (int r = 0; r < R3; ++r) w[272 * r] = v[q * R3 + r];
       }
       __syncthreads();
     }
@@ -308,8 +286,9 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
         const float4 t = s_tooth[i];
         const uint32_t packed = __float_as_uint(t.x);
         const int pa = (int)(packed & 0xffffu), pb = (int)(packed >> 16);
-        const c32 a = {re[pa], im[pa]};
-        const c32 b = {re[pb], -im[pb]};  // conj Z[M-k]
+        const c32 a = zc[pa];
+        const c32 zb = zc[pb];
+        const c32 b = {zb.x, -zb.y};  // conj Z[M-k]
         const c32 sm = cadd(a, b);
         const c32 o = mul_mi(csub(a, b));
         const c32 x = cadd(sm, cmul(c32{t.y, t.z}, o));

@@ -20,10 +20,11 @@
 //   fixed buffers; the burst size is read by the kernels from a device count
 //   in the slot, so one graph serves any burst up to `cap`.
 // * Dispatcher: one persistent host thread drains the queue in publish order:
-//   per burst it copies the count, launches the slot's graph on the stream's
-//   HIP stream, queues the copy of the results to pinned host memory and an
-//   event; it polls the events and records publish-to-results latency on the
-//   host clock.  Work of different streams overlaps on the GPU; within a
+//   per burst it writes the count to the slot's pinned word, launches the
+//   slot's graph on the stream's HIP stream (the graph reads the count and
+//   writes the results to pinned host memory itself) and records an event; it
+//   polls the events and records publish-to-results latency on the host
+//   clock.  Work of different streams overlaps on the GPU; within a
 //   stream bursts complete in order, so per-stream results come out in seq
 //   order (checked on read).
 // * Dry run (CG_PIPE_DRY_RUN): the same bookkeeping with no device work; a
@@ -57,6 +58,7 @@ struct PipeSlot {
   int16_t* frames = nullptr;
   int32_t* n_dev = nullptr;
   int32_t* n_host = nullptr;  // pinned
+  int32_t* n_host_dev = nullptr;  // device view of n_host
   char* ws = nullptr;
   float* y = nullptr;
   float* p0 = nullptr;
@@ -69,6 +71,8 @@ struct PipeSlot {
   int32_t* iters = nullptr;
   float* h_params = nullptr;   // pinned
   int32_t* h_status = nullptr;  // pinned
+  float* h_params_dev = nullptr;   // device views of the pinned results
+  int32_t* h_status_dev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;
@@ -119,12 +123,35 @@ constexpr size_t kLatKeep = 1 << 20;
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// The burst size enters the graph through pinned host memory (one thread
+// reads it over the bus into the slot's device count) and the results leave
+// it the same way, written straight into pinned host buffers: a burst costs
+// the dispatcher one graph launch and one event record.
+__global__ void count_in_kernel(const int32_t* __restrict__ host_n, int32_t* __restrict__ n) {
+  n[0] = host_n[0];
+}
+
+__global__ __launch_bounds__(256) void results_out_kernel(const int32_t* __restrict__ n_dev,
+                                                          int cap, const float4* __restrict__ params,
+                                                          const int32_t* __restrict__ status,
+                                                          float4* __restrict__ h_params,
+                                                          int32_t* __restrict__ h_status) {
+  int n = *n_dev;
+  n = n < cap ? n : cap;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    h_params[i] = params[i];
+    h_status[i] = status[i];
+  }
+}
+
 hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
   const cg_plan* p = ps.plan;
   hipStream_t s = ps.hs;
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  hipError_t le = launch_fft_teeth(p, sl.frames, cap, nullptr, sl.y, s, sl.n_dev);
+  hipLaunchKernelGGL(count_in_kernel, dim3(1), dim3(1), 0, s, sl.n_host_dev, sl.n_dev);
+  hipError_t le = hipGetLastError();
+  if (le == hipSuccess) le = launch_fft_teeth(p, sl.frames, cap, nullptr, sl.y, s, sl.n_dev);
   if ((ps.flags & CG_FIT_MASK) == CG_FIT_WARM_MLP) {
     if (le == hipSuccess) le = launch_mlp_infer(p->mlp, sl.y, cap, p->k, sl.p0, s, sl.n_dev);
     if (le == hipSuccess)
@@ -144,6 +171,13 @@ hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
     if (le == hipSuccess)
       le = launch_lm(sl.y, sl.p0, cap, p->k, 20, sl.params, sl.iters, sl.status, sl.chi2, s,
                      p->lm_chunk, sl.n_dev);
+  }
+  if (le == hipSuccess) {
+    const int blocks = (cap + 255) / 256 < 64 ? (cap + 255) / 256 : 64;
+    hipLaunchKernelGGL(results_out_kernel, dim3(blocks), dim3(256), 0, s, sl.n_dev, cap,
+                       reinterpret_cast<const float4*>(sl.params), sl.status,
+                       reinterpret_cast<float4*>(sl.h_params_dev), sl.h_status_dev);
+    le = hipGetLastError();
   }
   e = hipStreamEndCapture(s, &sl.graph);
   if (le != hipSuccess) return le;
@@ -192,6 +226,15 @@ hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
   if ((e = hipHostMalloc(&sl.n_host, sizeof(int32_t))) != hipSuccess) return e;
   if ((e = hipHostMalloc(&sl.h_params, (size_t)cap * 16)) != hipSuccess) return e;
   if ((e = hipHostMalloc(&sl.h_status, (size_t)cap * 4)) != hipSuccess) return e;
+  if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.n_host_dev), sl.n_host, 0)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.h_params_dev), sl.h_params, 0)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.h_status_dev), sl.h_status, 0)) !=
+      hipSuccess)
+    return e;
   if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) return e;
   return capture_slot(ps, sl, cap);
 }
@@ -200,13 +243,8 @@ hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
 hipError_t launch_burst(cg_pipeline* P, int si, int li) {
   PipeStream& ps = P->st[si];
   PipeSlot& sl = ps.slots[li];
-  *sl.n_host = sl.n;
-  hipError_t e = hipMemcpyAsync(sl.n_dev, sl.n_host, sizeof(int32_t), hipMemcpyHostToDevice, ps.hs);
-  if (e == hipSuccess) e = hipGraphLaunch(sl.exec, ps.hs);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(sl.h_params, sl.params, (size_t)sl.n * 16, hipMemcpyDeviceToHost, ps.hs);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(sl.h_status, sl.status, (size_t)sl.n * 4, hipMemcpyDeviceToHost, ps.hs);
+  *sl.n_host = sl.n;  // read by the graph's first kernel
+  hipError_t e = hipGraphLaunch(sl.exec, ps.hs);
   if (e == hipSuccess) e = hipEventRecord(sl.done, ps.hs);
   return e;
 }
