@@ -127,6 +127,31 @@ __device__ __forceinline__ void dft_r(c32* v) {
 
 __device__ __forceinline__ int padx(int i) { return i + (i >> 4); }
 
+// a * W_16^e for a compile-time e (after unrolling): quarter turns are sign
+// and swap changes, eighth turns two adds and two multiplies.
+__device__ __forceinline__ c32 mul_w16(c32 a, int e) {
+  e &= 15;
+  switch (e) {
+    case 0: return a;
+    case 4: return mul_mi(a);
+    case 8: return {-a.x, -a.y};
+    case 12: return {-a.y, a.x};
+    case 2: return {kC2 * (a.x + a.y), kC2 * (a.y - a.x)};
+    case 6: return {kC2 * (a.y - a.x), -kC2 * (a.x + a.y)};
+    case 10: return {-kC2 * (a.x + a.y), kC2 * (a.x - a.y)};
+    case 14: return {kC2 * (a.x - a.y), kC2 * (a.x + a.y)};
+    default: {
+      // W_16^e = cos(2 pi e / 16) - i sin(2 pi e / 16), odd e
+      constexpr float c[8] = {kC1, kS1, -kS1, -kC1, -kC1, -kS1, kS1, kC1};
+      constexpr float sn[8] = {kS1, kC1, kC1, kS1, -kS1, -kC1, -kC1, -kS1};
+      const int h = e >> 1;
+      return cmul(a, c32{c[h], -sn[h]});
+    }
+  }
+}
+
+
+
 template <int LOGM>
 struct FftShape {
   static constexpr int M = 1 << LOGM;
@@ -194,12 +219,12 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
   c32 w2[15];
 #pragma unroll
   for (int r = 1; r < 16; ++r) w2[r - 1] = tw[e2 * r];
-  c32 w3[NB3 > 0 ? NB3 * (R3 - 1) : 1];
+  // Pass 3 twiddles W_M^((j + T q) r) = W_M^(j r) W_16^(q r): only the first
+  // factor is kept per thread, the second is a compile-time constant.
+  c32 w3[R3 > 1 ? R3 - 1 : 1];
   if constexpr (R3 > 1) {
 #pragma unroll
-    for (int q = 0; q < NB3; ++q)
-#pragma unroll
-      for (int r = 1; r < R3; ++r) w3[q * (R3 - 1) + r - 1] = tw[2 * (j + T * q) * r];
+    for (int r = 1; r < R3; ++r) w3[r - 1] = tw[2 * j * r];
   }
 
   // first group's samples.  Threads of frames past the end read the last
@@ -272,7 +297,7 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
       for (int q = 0; q < NB3; ++q) {
         const int jp = j + T * q;
 #pragma unroll
-        for (int r = 1; r < R3; ++r) v[q * R3 + r] = cmul(v[q * R3 + r], w3[q * (R3 - 1) + r - 1]);
+        for (int r = 1; r < R3; ++r) v[q * R3 + r] = mul_w16(cmul(v[q * R3 + r], w3[r - 1]), q * r);
         dft_r<R3>(v + q * R3);
         c32* w = zc + jp + (jp >> 4);
 #pragma unroll
