@@ -152,6 +152,21 @@ __device__ __forceinline__ c32 mul_w16(c32 a, int e) {
 
 
 
+// Ordering of the LDS exchanges between passes.  With T <= 64 every frame
+// lives inside one wavefront: its lanes run in lock step and the LDS executes
+// one wavefront's accesses in issue order, so a compiler-level fence at
+// wavefront scope is all a pass needs before reading what the previous pass
+// wrote.  Larger frames span several wavefronts and take a block barrier.
+template <int T>
+__device__ __forceinline__ void frame_sync() {
+  if constexpr (T <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 template <int LOGM>
 struct FftShape {
   static constexpr int M = 1 << LOGM;
@@ -240,6 +255,8 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
     for (int r = 0; r < 16; ++r) raw[r] = __builtin_nontemporal_load(src + r * T);
   }
 
+  __syncthreads();  // the per-tooth table is filled by the whole block
+
   for (; g < ngroups; g += gridDim.x) {
     const int64_t frame = g * FPB + fl;
     const bool live = frame < n_frames;
@@ -260,20 +277,20 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 
     // ---- pass 1: radix 16, Ns = 1 ----
     dft16(v);
-    __syncthreads();  // the previous group's epilogue has read the points
+    frame_sync<T>();  // the previous group's epilogue has read the points
     {
       c32* w = zc + 17 * j;  // padx(16 j + r) = 17 j + r
 #pragma unroll
       for (int r = 0; r < 16; ++r) w[r] = v[r];
     }
-    __syncthreads();
+    frame_sync<T>();
     // ---- pass 2: radix 16, Ns = 16 ----
     {
       constexpr int S2 = T + T / 16;
       const c32* rd = zc + j + (j >> 4);
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = rd[r * S2];
-      __syncthreads();
+      frame_sync<T>();
 #pragma unroll
       for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w2[r - 1]);
       dft16(v);
@@ -282,7 +299,7 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 #pragma unroll
       for (int r = 0; r < 16; ++r) w[17 * r] = v[r];
     }
-    __syncthreads();
+    frame_sync<T>();
     // ---- pass 3: radix M/256, Ns = 256 ----
     if constexpr (R3 > 1) {
 #pragma unroll
@@ -292,7 +309,7 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 #pragma unroll
         for (int r = 0; r < R3; ++r) v[q * R3 + r] = rd[272 * r];
       }
-      __syncthreads();
+      frame_sync<T>();
 #pragma unroll
       for (int q = 0; q < NB3; ++q) {
         const int jp = j + T * q;
@@ -303,7 +320,7 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 #pragma unroll
         for (int r = 0; r < R3; ++r) w[272 * r] = v[q * R3 + r];
       }
-      __syncthreads();
+      frame_sync<T>();
     }
     // ---- untangle the real spectrum at the tooth bins, amplitude, / ref ----
     if (live) {
