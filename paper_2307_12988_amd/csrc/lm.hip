@@ -324,23 +324,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   }
 }
 
-__global__ void zero_i32_kernel(int32_t* p) { *p = 0; }
 
-__global__ void fallback_select_kernel(const float* __restrict__ chi2, int64_t nf, int k,
-                                       float thr2, int32_t* __restrict__ flags,
-                                       int32_t* __restrict__ idx, int32_t* __restrict__ count,
-                                       const int32_t* __restrict__ dev_n) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One block lists the fallback frames: every thread scans a strided share of
+// the batch and appends through a counter in LDS, and the count is written
+// once at the end, so no separate kernel has to clear a global counter first
+// (the list order is not specified).
+__global__ __launch_bounds__(1024) void fallback_select_kernel(
+    const float* __restrict__ chi2, int64_t nf, float thr2, int32_t* __restrict__ flags,
+    int32_t* __restrict__ idx, int32_t* __restrict__ count, const int32_t* __restrict__ dev_n) {
+  __shared__ int32_t s_count;
   if (dev_n) {
     const int64_t dn = *dev_n;
     nf = dn < nf ? dn : nf;
   }
-  if (f >= nf) return;
-  // RMS residual sqrt(chi2 / (k - 4)) > 2 sigma  <=>  chi2 > 4 sigma^2 (k - 4)
-  const float c = chi2[f];
-  const bool bad = !isfinite(c) || c > thr2;
-  flags[f] = bad ? 1 : 0;
-  if (bad) idx[atomicAdd(count, 1)] = (int32_t)f;
+  if (threadIdx.x == 0) s_count = 0;
+  __syncthreads();
+  for (int64_t f = threadIdx.x; f < nf; f += blockDim.x) {
+    // RMS residual sqrt(chi2 / (k - 4)) > 2 sigma  <=>  chi2 > 4 sigma^2 (k - 4)
+    const float c = chi2[f];
+    const bool bad = !isfinite(c) || c > thr2;
+    flags[f] = bad ? 1 : 0;
+    if (bad) idx[atomicAdd(&s_count, 1)] = (int32_t)f;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *count = s_count;
 }
 
 }  // namespace
@@ -348,13 +355,11 @@ __global__ void fallback_select_kernel(const float* __restrict__ chi2, int64_t n
 hipError_t launch_fallback_select(const float* chi2, int64_t nf, int k, float noise_floor,
                                   int32_t* flags, int32_t* idx, int32_t* count, hipStream_t s,
                                   const int32_t* dev_n) {
-  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, s, count);
+  if (nf > 0x7fffffff) return hipErrorInvalidValue;
   const double dof = k > 4 ? (double)(k - 4) : 1.0;
   const float thr2 = (float)(4.0 * (double)noise_floor * (double)noise_floor * dof);
-  const int64_t blocks = (nf + 255) / 256;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fallback_select_kernel, dim3((unsigned)blocks), dim3(256), 0, s, chi2, nf, k,
-                     thr2, flags, idx, count, dev_n);
+  hipLaunchKernelGGL(fallback_select_kernel, dim3(1), dim3(1024), 0, s, chi2, nf, thr2, flags,
+                     idx, count, dev_n);
   return hipGetLastError();
 }
 

@@ -45,7 +45,10 @@ def _run_full(plan, frames_np):
 
 @pytest.mark.parametrize("n,k,nf", [(512, 64, 37), (512, 128, 16), (1024, 100, 129),
                                     (2048, 220, 333), (4096, 220, 101), (8192, 440, 17),
-                                    (8192, 64, 5)])
+                                    (8192, 64, 5),
+                                    # more frame groups than resident blocks, so the
+                                    # persistent blocks loop, with a ragged last group
+                                    (2048, 220, 20001), (512, 128, 70001)])
 def test_teeth_all_frame_lengths(n, k, nf):
     _say(f"teeth n={n} k={k} nf={nf}")
     spec = synth.StreamSpec(name="t", n=n, fs=1.1e9, bins=synth.tooth_bins_interleaved(n, k),
