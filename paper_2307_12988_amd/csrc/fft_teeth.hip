@@ -13,11 +13,16 @@
 //     X[k] = (Z[k] + conj Z[M-k]) / 2 - i W_N^k (Z[k] - conj Z[M-k]) / 2.
 //   Only the K tooth bins are untangled; the full spectrum never leaves LDS.
 // * Stockham autosort passes, 16 points per thread held in registers: two
-//   radix-16 passes and one radix-M/256 pass (M = 256 .. 4096), so each frame
-//   makes two or three LDS exchanges.  Threads per frame T = M/16; a 256-thread
-//   workgroup holds 256/T frames.  LDS holds interleaved complex points
-//   (one 64-bit access per point) with one padding point per 16 so the
-//   strided pass-1 stores are bank-conflict free.
+//   radix-16 passes and one radix-M/256 pass (M = 256 .. 4096).  Threads per
+//   frame T = M/16; a 256-thread workgroup holds 256/T frames.  LDS holds
+//   interleaved complex points (one 64-bit access per point) with one padding
+//   point per 16 so the strided pass-1 stores are bank-conflict free.
+// * When a frame spans 2 or 4 rows of one wavefront (M = 512, 1024) the last
+//   pass needs no LDS: its butterfly inputs sit in one register of the
+//   frame's rows, and the lane swaps of gfx950 (permlane16/32 swap) transpose
+//   them into one lane.  A frame then goes through LDS once between passes
+//   1 and 2 and once more for the tooth gather; larger frames span several
+//   wavefronts and exchange through LDS before every pass.
 // * Twiddles come from a table of W_N^e built on the host in FP64 and rounded
 //   once to FP32 (no fast-math sin/cos on the device).
 // * Persistent blocks: the grid is sized to what fits on the chip, each block
@@ -152,6 +157,42 @@ __device__ __forceinline__ c32 mul_w16(c32 a, int e) {
 
 
 
+// Lane exchanges of gfx950 (one row = 16 lanes of a wavefront).  swap32
+// trades lanes 32..63 of a with lanes 0..31 of b; swap16 trades rows 1 and 3
+// of a with rows 0 and 2 of b.
+__device__ __forceinline__ float2 swap_pair32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return {__uint_as_float(r[0]), __uint_as_float(r[1])};
+}
+__device__ __forceinline__ float2 swap_pair16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return {__uint_as_float(r[0]), __uint_as_float(r[1])};
+}
+__device__ __forceinline__ void swap32(c32& a, c32& b) {
+  const float2 x = swap_pair32(a.x, b.x), y = swap_pair32(a.y, b.y);
+  a = {x.x, y.x};
+  b = {x.y, y.y};
+}
+__device__ __forceinline__ void swap16(c32& a, c32& b) {
+  const float2 x = swap_pair16(a.x, b.x), y = swap_pair16(a.y, b.y);
+  a = {x.x, y.x};
+  b = {x.y, y.y};
+}
+
+// Transpose R registers against the R rows of a frame (R = 2 or 4): on
+// return, register t of row s holds what register s of row t held.
+template <int R>
+__device__ __forceinline__ void rows_transpose(c32* x) {
+  if constexpr (R == 4) {
+    swap32(x[0], x[2]);
+    swap32(x[1], x[3]);
+  }
+  swap16(x[0], x[1]);
+  if constexpr (R == 4) swap16(x[2], x[3]);
+}
+
 // Ordering of the LDS exchanges between passes.  With T <= 64 every frame
 // lives inside one wavefront: its lanes run in lock step and the LDS executes
 // one wavefront's accesses in issue order, so a compiler-level fence at
@@ -175,13 +216,30 @@ struct FftShape {
   static constexpr int PM = M + M / 16;     // padded plane length
   static constexpr int R3 = M / 256;        // radix of the last pass (1 = none)
   static constexpr int NB3 = R3 > 1 ? 16 / R3 : 0;  // last-pass butterflies per thread
+  // the last pass by lane exchanges: a frame of 2 or 4 rows in one wavefront
+  static constexpr bool LANE_PASS3 = R3 == 2 || R3 == 4;
+  // LDS position of spectrum bin k.  The lane pass stores the spectrum with
+  // consecutive lanes on consecutive bins, so it needs no padding, and an
+  // evenly spaced comb with an odd spacing then gathers from distinct banks;
+  // the LDS passes leave it in the padded layout.
+  static __device__ __forceinline__ int fpos(int k) { return LANE_PASS3 ? k : k + (k >> 4); }
   static constexpr size_t PLANE_BYTES = sizeof(float) * 2 * FPB * PM;  // complex points
 };
 
-// Dynamic LDS: the complex points of FPB frames, then one float4
-// per tooth {packed padded LDS offsets of Z[k] and Z[M-k], Re W_N^k, Im W_N^k,
-// 0.5 / ref}.
+// Tooth constants: one float4 per tooth in LDS, {packed padded LDS offsets of
+// Z[k] and Z[M-k], Re W_N^k, Im W_N^k, 0.5 / ref}.  With TPT > 0 thread j of
+// a frame handles the teeth j + T u, u < TPT, and also keeps their packed
+// offsets in registers, so a frame's gathers and constant reads are issued
+// together (one LDS round trip); TPT = 0 (more than 4 teeth per thread) walks
+// the table.
 template <int LOGM>
+int fft_teeth_per_thread(int k) {
+  const int per = (k + FftShape<LOGM>::T - 1) / FftShape<LOGM>::T;
+  return per <= 1 ? 1 : per <= 2 ? 2 : per <= 4 ? 4 : 0;
+}
+
+// Dynamic LDS: the complex points of FPB frames, then the tooth table.
+template <int LOGM, int TPT>
 size_t fft_lds_bytes(int k) {
   return FftShape<LOGM>::PLANE_BYTES + sizeof(float4) * (size_t)k;
 }
@@ -191,10 +249,10 @@ size_t fft_lds_bytes(int k) {
 // is transformed, the 64 bytes per thread of the next group are already in
 // flight (issued right after the current group's samples are converted), so
 // HBM sees a steady stream of loads instead of one burst per block.  Nothing
-// else is read from global memory inside the loop: twiddles live in
-// registers and the per-tooth constants in LDS, so waiting for one load never
-// means waiting for the prefetch.
-template <int LOGM>
+// else is read from global memory inside the loop: twiddles and tooth
+// constants live in registers (or LDS), so waiting for one load never means
+// waiting for the prefetch.
+template <int LOGM, int TPT>
 __global__ __launch_bounds__(256) void fft_teeth_kernel(
     const int32_t* __restrict__ frames, int64_t n_frames, const int32_t* __restrict__ bins,
     const float* __restrict__ half_inv_ref, const c32* __restrict__ tw, int k_teeth,
@@ -220,13 +278,27 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
   c32* zc = s_c + fl * PM;
 
   // per-tooth constants
-  for (int i = tid; i < k_teeth; i += 256) {
+  auto tooth_const = [&](int i) {
     const int kb = bins[i];
     const int ia = kb & (M - 1);
     const int ib = (M - kb) & (M - 1);
-    const uint32_t packed = (uint32_t)padx(ia) | ((uint32_t)padx(ib) << 16);
+    const uint32_t packed = (uint32_t)S::fpos(ia) | ((uint32_t)S::fpos(ib) << 16);
     const c32 w = tw[kb];
-    s_tooth[i] = make_float4(__uint_as_float(packed), w.x, w.y, half_inv_ref[i]);
+    return make_float4(__uint_as_float(packed), w.x, w.y, half_inv_ref[i]);
+  };
+  for (int i = tid; i < k_teeth; i += 256) s_tooth[i] = tooth_const(i);
+  // teeth past the end repeat the last one; their results are not stored
+  // (as byte addresses of Z[k] and Z[M-k] in this frame's LDS plane)
+  const char* t_za[TPT > 0 ? TPT : 1];
+  const char* t_zb[TPT > 0 ? TPT : 1];
+  if constexpr (TPT > 0) {
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+      const int i = j + T * u;
+      const uint32_t packed = __float_as_uint(tooth_const(i < k_teeth ? i : k_teeth - 1).x);
+      t_za[u] = reinterpret_cast<const char*>(zc + (packed & 0xffffu));
+      t_zb[u] = reinterpret_cast<const char*>(zc + (packed >> 16));
+    }
   }
   // twiddles of pass 2 (W_256^(jm r) = W_N^(e2 r)) and pass 3 (W_M^(jp r))
   const int jm = j & 15;
@@ -294,14 +366,37 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
 #pragma unroll
       for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w2[r - 1]);
       dft16(v);
-      const int base = (j >> 4) * 256 + jm;
-      c32* w = zc + base + (base >> 4);
+      if constexpr (!S::LANE_PASS3) {
+        const int base = (j >> 4) * 256 + jm;
+        c32* w = zc + base + (base >> 4);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) w[17 * r] = v[r];
+        for (int r = 0; r < 16; ++r) w[17 * r] = v[r];
+      }
     }
-    frame_sync<T>();
+    if constexpr (!S::LANE_PASS3) frame_sync<T>();
     // ---- pass 3: radix M/256, Ns = 256 ----
-    if constexpr (R3 > 1) {
+    if constexpr (S::LANE_PASS3) {
+      // Register r of row s now holds point 256 s + jm + 16 r, so the R3
+      // inputs of a butterfly sit in one register of the frame's R3 rows.
+      // A transpose of each run of R3 registers against the rows hands row
+      // s the butterfly of register q R3 + s: point j + T q and its
+      // partners, the same butterflies and twiddles as the LDS form below.
+#pragma unroll
+      for (int q = 0; q < NB3; ++q) {
+        rows_transpose<R3>(v + q * R3);
+#pragma unroll
+        for (int r = 1; r < R3; ++r) v[q * R3 + r] = mul_w16(cmul(v[q * R3 + r], w3[r - 1]), q * r);
+        dft_r<R3>(v + q * R3);
+      }
+      frame_sync<T>();  // pass 2 has read the points
+#pragma unroll
+      for (int q = 0; q < NB3; ++q) {
+        c32* w = zc + j + T * q;
+#pragma unroll
+        for (int r = 0; r < R3; ++r) w[256 * r] = v[q * R3 + r];
+      }
+      frame_sync<T>();
+    } else if constexpr (R3 > 1) {
 #pragma unroll
       for (int q = 0; q < NB3; ++q) {
         const int jp = j + T * q;
@@ -323,31 +418,47 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
       frame_sync<T>();
     }
     // ---- untangle the real spectrum at the tooth bins, amplitude, / ref ----
-    if (live) {
+    const int64_t row = frame * k_teeth;
+    auto tooth_out = [&](const float4 t, c32 a, c32 zb, int i) {
+      const c32 b = {zb.x, -zb.y};  // conj Z[M-k]
+      const c32 sm = cadd(a, b);
+      const c32 o = mul_mi(csub(a, b));
+      const c32 x = cadd(sm, cmul(c32{t.y, t.z}, o));
+      const float r2 = __builtin_amdgcn_sqrtf(x.x * x.x + x.y * x.y);  // 2 |X[k]|
+      if (out_mag) out_mag[row + i] = 0.5f * r2;
+      if (out_y) out_y[row + i] = r2 * t.w;
+    };
+    if constexpr (TPT > 0) {
+      // all gathers of the frame at once, one LDS round trip
+      c32 za[TPT], zb[TPT];
+      float4 tc[TPT];
+#pragma unroll
+      for (int u = 0; u < TPT; ++u) {
+        const int i = j + T * u;
+        tc[u] = s_tooth[i < k_teeth ? i : k_teeth - 1];
+        za[u] = *reinterpret_cast<const c32*>(t_za[u]);
+        zb[u] = *reinterpret_cast<const c32*>(t_zb[u]);
+      }
+      if (live) {
+#pragma unroll
+        for (int u = 0; u < TPT; ++u)
+          if (j + T * u < k_teeth) tooth_out(tc[u], za[u], zb[u], j + T * u);
+      }
+    } else if (live) {
       for (int i = j; i < k_teeth; i += T) {
         const float4 t = s_tooth[i];
         const uint32_t packed = __float_as_uint(t.x);
-        const int pa = (int)(packed & 0xffffu), pb = (int)(packed >> 16);
-        const c32 a = zc[pa];
-        const c32 zb = zc[pb];
-        const c32 b = {zb.x, -zb.y};  // conj Z[M-k]
-        const c32 sm = cadd(a, b);
-        const c32 o = mul_mi(csub(a, b));
-        const c32 x = cadd(sm, cmul(c32{t.y, t.z}, o));
-        const float r2 = __builtin_amdgcn_sqrtf(x.x * x.x + x.y * x.y);  // 2 |X[k]|
-        const int64_t idx = frame * k_teeth + i;
-        if (out_mag) out_mag[idx] = 0.5f * r2;
-        if (out_y) out_y[idx] = r2 * t.w;
+        tooth_out(t, zc[packed & 0xffffu], zc[packed >> 16], i);
       }
     }
   }
 }
 
-template <int LOGM>
-int max_blocks_t(const cg_plan* p) {
+template <int LOGM, int TPT>
+int max_blocks_tt(const cg_plan* p) {
   int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fft_teeth_kernel<LOGM>, 256,
-                                                   fft_lds_bytes<LOGM>(p->k)) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fft_teeth_kernel<LOGM, TPT>, 256,
+                                                   fft_lds_bytes<LOGM, TPT>(p->k)) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
           hipSuccess ||
       per_cu <= 0 || cus <= 0)
@@ -356,18 +467,39 @@ int max_blocks_t(const cg_plan* p) {
 }
 
 template <int LOGM>
-hipError_t launch_t(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
-                    float* out_y, hipStream_t s, const int32_t* dev_n) {
+int max_blocks_t(const cg_plan* p) {
+  switch (fft_teeth_per_thread<LOGM>(p->k)) {
+    case 1: return max_blocks_tt<LOGM, 1>(p);
+    case 2: return max_blocks_tt<LOGM, 2>(p);
+    case 4: return max_blocks_tt<LOGM, 4>(p);
+    default: return max_blocks_tt<LOGM, 0>(p);
+  }
+}
+
+template <int LOGM, int TPT>
+hipError_t launch_tt(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
+                     float* out_y, hipStream_t s, const int32_t* dev_n) {
   using S = FftShape<LOGM>;
   int64_t blocks = (nf + S::FPB - 1) / S::FPB;
   if (p->fft_blocks > 0 && blocks > p->fft_blocks) blocks = p->fft_blocks;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(fft_teeth_kernel<LOGM>, dim3((unsigned)blocks), dim3(256),
-                     fft_lds_bytes<LOGM>(p->k), s, reinterpret_cast<const int32_t*>(frames), nf,
-                     p->d_bins, p->d_half_inv_ref, reinterpret_cast<const c32*>(p->d_tw), p->k,
-                     out_mag, out_y, dev_n);
+  fft_teeth_kernel<LOGM, TPT><<<dim3((unsigned)blocks), dim3(256), fft_lds_bytes<LOGM, TPT>(p->k),
+                                 s>>>(reinterpret_cast<const int32_t*>(frames), nf, p->d_bins,
+                                      p->d_half_inv_ref, reinterpret_cast<const c32*>(p->d_tw),
+                                      p->k, out_mag, out_y, dev_n);
   return hipGetLastError();
+}
+
+template <int LOGM>
+hipError_t launch_t(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
+                    float* out_y, hipStream_t s, const int32_t* dev_n) {
+  switch (fft_teeth_per_thread<LOGM>(p->k)) {
+    case 1: return launch_tt<LOGM, 1>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 2: return launch_tt<LOGM, 2>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 4: return launch_tt<LOGM, 4>(p, frames, nf, out_mag, out_y, s, dev_n);
+    default: return launch_tt<LOGM, 0>(p, frames, nf, out_mag, out_y, s, dev_n);
+  }
 }
 
 }  // namespace

@@ -48,7 +48,7 @@ def _run_full(plan, frames_np):
                                     (8192, 64, 5),
                                     # more frame groups than resident blocks, so the
                                     # persistent blocks loop, with a ragged last group
-                                    (2048, 220, 20001), (512, 128, 70001)])
+                                    (2048, 220, 20001), (1024, 200, 40001), (512, 128, 70001)])
 def test_teeth_all_frame_lengths(n, k, nf):
     _say(f"teeth n={n} k={k} nf={nf}")
     spec = synth.StreamSpec(name="t", n=n, fs=1.1e9, bins=synth.tooth_bins_interleaved(n, k),
