@@ -80,32 +80,48 @@ __device__ __forceinline__ double rcp1_d(double x) {
 // D = 1 + u^2, s = d / D^2,
 //   df/dc = (-4 b / w) s u,   df/dw = (-2 b / w) s u^2,
 //   df/dd = (-b) / D,         df/db = 1 - d / D.
+//
+// Per tooth the FP64 part is u (from the lane's first tooth plus a constant
+// offset), D, 1 / D and the residual r = (y - b) + (b d) / D, which is
+// y - f(x) rounded differently; the FP32 Jacobian factors start from FP32
+// copies of the same quantities.
 template <int G, int Q>
 __device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, double c, double w,
                                          double d, double b, Sums& s) {
-  int gl = lane_id() & (G - 1);
-  asm volatile("" : "+v"(gl));  // slot indices are rebuilt per call, not kept live
+  const int gl = lane_id() & (G - 1);
   float acc[14];
 #pragma unroll
   for (int j = 0; j < 14; ++j) acc[j] = 0.0f;
   double chi2 = 0.0;
   const double two_iw = 2.0 * rcp_d(w);
-  const double c_iw = c * two_iw;
+  const double u0 = fma((double)gl, two_iw, -c * two_iw);  // u at tooth gl
+  const double bd = b * d;
+  const float two_iwf = (float)two_iw, u0f = (float)u0, df = (float)d;
+  const double step = (double)G * two_iw;
+  double u_prev = u0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    // The empty asm statements pin the slots in program order: each slot's
-    // index passes through one before its arithmetic and its sums pass
-    // through one after it.  Left alone, the compiler evaluates the FP64 part
-    // of every slot first and keeps all of it live (about 100 extra VGPRs).
-    int i = gl + G * q;
-    asm volatile("" : "+v"(i));
-    const double u = fma((double)i, two_iw, -c_iw);
+    // The empty asm statements pin pairs of slots in program order: the u of
+    // the pair's first slot passes through one before the pair's arithmetic
+    // (the second slot's u is derived from it) and the sums pass through one
+    // after the pair.  Left alone, the compiler evaluates the FP64 part of
+    // every slot first and keeps all of it live (about 100 extra VGPRs); two
+    // slots at a time give the scheduler two independent chains.
+    const int i = gl + G * q;
+    double u;
+    if (q % 2 == 0) {
+      u = fma((double)(G * q), two_iw, u0);
+      asm volatile("" : "+v"(u));
+    } else {
+      u = u_prev + step;
+    }
+    u_prev = u;
     const double den = fma(u, u, 1.0);
     const double inv = rcp1_d(den);
-    const double qd = d * inv;
-    const double f = fma(-b, qd, b);
-    double r = (double)yv[q] - f;
-    const float uf = (float)u, invf = (float)inv, qf = (float)qd;
+    double r = fma(bd, inv, (double)yv[q] - b);
+    const float invf = (float)inv;
+    const float uf = fmaf((float)(G * q), two_iwf, u0f);
+    const float qf = df * invf;  // d / D
     float jc = qf * invf * uf;   // s u
     float jw = jc * uf;          // s u^2
     float jd = invf;             // 1 / D
@@ -134,7 +150,8 @@ __device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, double c, 
     acc[11] = fmaf(jw, rf, acc[11]);
     acc[12] = fmaf(jd, rf, acc[12]);
     acc[13] = fmaf(jb, rf, acc[13]);
-    asm volatile(""
+    if (q % 2 == 1 || q == Q - 1)
+      asm volatile(""
                  : "+v"(chi2), "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]),
                    "+v"(acc[4]), "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]),
                    "+v"(acc[9]), "+v"(acc[10]), "+v"(acc[11]), "+v"(acc[12]), "+v"(acc[13]));
@@ -143,7 +160,7 @@ __device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, double c, 
 #pragma unroll
   for (int j = 0; j < 14; ++j) sum[j] = sum_group<G>(acc[j]);
   // column factors: c, w, d carry al, be, ga; b carries 1
-  const float bf = (float)b, two_iwf = (float)two_iw;
+  const float bf = (float)b;
   const float al = -2.0f * bf * two_iwf, be = -bf * two_iwf, ga = -bf;
   s.a[0] = sum[0] * (al * al);
   s.a[1] = sum[1] * (al * be);
