@@ -170,31 +170,38 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
     if (i < k) hi = keys[q] > hi ? keys[q] : hi;
   }
   hi = max16(hi);
+  // Teeth past the end take the largest key: no key is below it and no
+  // probe above it, so they never count and the counts need no mask.
+#pragma unroll
+  for (int q = 0; q < Q; ++q) keys[q] = gl + 16 * q < k ? keys[q] : 0xffffffffu;
   int c_lo = 0, c_hi = k;
   while (lo < hi && c_hi - c_lo > 1) {
     const uint32_t mid = lo + ((hi - lo) >> 1) + 1u;  // lo < mid <= hi
-    int c = 0;
+    // One compare and one add with carry per key, in two interleaved
+    // chains; the empty asm keeps the compiler from packing the comparisons
+    // into a bit mask and popcount.
+    uint32_t ca = 0, cb = 0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int i = gl + 16 * q;
-      c += (i < k) && (keys[q] < mid);
+    for (int q = 0; q + 1 < Q; q += 2) {
+      ca += (uint32_t)(keys[q] < mid);
+      cb += (uint32_t)(keys[q + 1] < mid);
+      asm volatile("" : "+v"(ca), "+v"(cb));
     }
-    c = sum16(c);
-    if (c <= r) {
+    if constexpr (Q % 2 == 1) ca += (uint32_t)(keys[Q - 1] < mid);
+    uint32_t c = (uint32_t)sum16((int)(ca + cb));
+    if ((int)c <= r) {
       lo = mid;
-      c_lo = c;
+      c_lo = (int)c;
     } else {
       hi = mid - 1u;
-      c_hi = c;
+      c_hi = (int)c;
     }
   }
   if (lo < hi) {
     uint32_t m = 0xffffffffu;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int i = gl + 16 * q;
-      if (i < k && keys[q] >= lo && keys[q] < m) m = keys[q];
-    }
+    for (int q = 0; q < Q; ++q)
+      if (keys[q] >= lo && keys[q] < m) m = keys[q];
     lo = min16(m);
   }
   const uint32_t prefix = lo;
