@@ -79,17 +79,21 @@ def _log(msg):
 def _gen(args):
     spec, nf, seed, b = args
     bt = synth.make_batch(spec, nf, seed=seed, batch_index=b)
-    return b, bt.frames, bt.ref_frames
+    return b, bt.frames, bt.ref_frames, (bt.centre, bt.width)
 
 
-def make_pool(spec, nf, n_batches, workers):
+def make_pool(spec, nf, n_batches, workers, truth=False):
+    """Synthetic batches (and, with truth, each batch's true dip centres and
+    widths)."""
     frames = [None] * n_batches
+    truths = [None] * n_batches
     ref = None
     with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-        for b, fr, rf in ex.map(_gen, [(spec, nf, SEED, b) for b in range(n_batches)]):
+        for b, fr, rf, tr in ex.map(_gen, [(spec, nf, SEED, b) for b in range(n_batches)]):
             frames[b] = fr
+            truths[b] = tr
             ref = rf
-    return frames, ref
+    return (frames, ref, truths) if truth else (frames, ref)
 
 
 def lm_flops(k, iters):
@@ -240,17 +244,18 @@ def warm_forms(args, torch, cg, dev):
     """The learned warm start beside the plain cold-start path on the same
     frames: spectra of the network's training distribution (a seed used for
     neither training nor hold-out), whole path per batch.  Forms: cold (7x7
-    median start point + LM <= 20 iterations), warm with the 2-iteration
-    polish, and warm with the polish run to convergence (<= 20 iterations);
-    the warm forms fall back to the cold start when the polished fit's RMS
-    residual exceeds twice the noise floor.  Accuracy: centre difference to
-    the cold fit over the first batch, and to the FP64 oracle on a sample."""
+    median start point + LM <= 20 iterations), warm with a 2- and a
+    3-iteration polish, and warm with the polish run to convergence (<= 20
+    iterations); the warm forms fall back to the cold start when the polished
+    fit's RMS residual exceeds twice the noise floor.  Accuracy: centre
+    difference to the cold fit over the first batch, to the FP64 oracle on a
+    sample, and to the generator's true centre over the first batch."""
     spec = synth.spec_learned()
     nf, n, k = args.frames, spec.n, spec.k
     weights = os.path.join(ROOT, "paper_2307_12988_amd", "data", "warmstart_learned.npz")
     w = np.load(weights)
     _log(f"generating {args.pool} batches of {nf} x {n} int16 (learned distribution) ...")
-    pool_np, ref_np = make_pool(spec, nf, args.pool, workers=args.pool)
+    pool_np, ref_np, truths = make_pool(spec, nf, args.pool, workers=args.pool, truth=True)
     pool = [torch.from_numpy(fr).to(dev) for fr in pool_np]
     plan = cg.Plan(n, spec.fs, spec.bins, np.ones(k, dtype=np.float32))
     ref_gpu = plan.reference_from_frames(torch.from_numpy(ref_np).to(dev)).cpu().numpy()
@@ -261,7 +266,7 @@ def warm_forms(args, torch, cg, dev):
     iters = torch.empty((nf,), dtype=torch.int32, device=dev)
     status = torch.empty((nf,), dtype=torch.int32, device=dev)
     forms = [("cold", cg.FIT_COLD, 2), ("warm_polish2", cg.FIT_WARM_MLP, 2),
-             ("warm_polish20", cg.FIT_WARM_MLP, 20)]
+             ("warm_polish3", cg.FIT_WARM_MLP, 3), ("warm_polish20", cg.FIT_WARM_MLP, 20)]
     res = {}
     for name, flag, polish in forms:
         plan.set_polish_iters(polish)
@@ -307,6 +312,11 @@ def warm_forms(args, torch, cg, dev):
                 "centre_vs_cold": {"frames": int(conv.sum()),
                                    "within_1e-3_fwhm": float(np.mean(err[conv] <= 1e-3)),
                                    "median_fwhm": float(np.median(err[conv]))}}
+        # every frame of the first batch against the generator's true centre
+        et = np.abs(r["params"][:, 0] - truths[0][0]) / truths[0][1]
+        line["centre_vs_truth"] = {"frames": int(nf), "median_fwhm": float(np.median(et)),
+                                   "p90_fwhm": float(np.percentile(et, 90)),
+                                   "p99_fwhm": float(np.percentile(et, 99))}
         if orc is not None:
             m = orc["n"] - 3  # the oracle's slice ends at its own last frame
             oc = orc["status"][:m] == 0
