@@ -349,7 +349,7 @@ def multistream(args, torch, cg, dev):
         gen = list(ex.map(_gen, jobs))
     plans, pools, fl = [], [], []
     tune = {}
-    for i, (sp, (_, frames, ref_frames)) in enumerate(zip(specs, gen)):
+    for i, (sp, (_, frames, ref_frames, _truth)) in enumerate(zip(specs, gen)):
         pl = cg.Plan(sp.n, sp.fs, sp.bins, np.ones(sp.k, dtype=np.float32))
         pl.set_reference(pl.reference_from_frames(torch.from_numpy(ref_frames).to(dev)).cpu().numpy())
         pool = torch.from_numpy(frames).to(dev)
