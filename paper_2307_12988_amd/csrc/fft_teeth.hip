@@ -226,12 +226,12 @@ struct FftShape {
   static constexpr size_t PLANE_BYTES = sizeof(float) * 2 * FPB * PM;  // complex points
 };
 
-// Tooth constants: one float4 per tooth in LDS, {packed padded LDS offsets of
-// Z[k] and Z[M-k], Re W_N^k, Im W_N^k, 0.5 / ref}.  With TPT > 0 thread j of
-// a frame handles the teeth j + T u, u < TPT, and also keeps their packed
-// offsets in registers, so a frame's gathers and constant reads are issued
-// together (one LDS round trip); TPT = 0 (more than 4 teeth per thread) walks
-// the table.
+// Tooth constants: one float4 per tooth in LDS, {LDS positions of Z[k] and
+// Z[M-k] packed in two 16-bit fields, Re W_N^k, Im W_N^k, 0.5 / ref}.  With
+// TPT > 0 thread j of a frame handles the teeth j + T u, u < TPT, and also
+// keeps their gather addresses in registers, so a frame's gathers and constant
+// reads are issued together (one LDS round trip); TPT = 0 (more than 4 teeth
+// per thread) walks the table.
 template <int LOGM>
 int fft_teeth_per_thread(int k) {
   const int per = (k + FftShape<LOGM>::T - 1) / FftShape<LOGM>::T;
@@ -239,7 +239,7 @@ int fft_teeth_per_thread(int k) {
 }
 
 // Dynamic LDS: the complex points of FPB frames, then the tooth table.
-template <int LOGM, int TPT>
+template <int LOGM>
 size_t fft_lds_bytes(int k) {
   return FftShape<LOGM>::PLANE_BYTES + sizeof(float4) * (size_t)k;
 }
@@ -287,8 +287,9 @@ __global__ __launch_bounds__(256) void fft_teeth_kernel(
     return make_float4(__uint_as_float(packed), w.x, w.y, half_inv_ref[i]);
   };
   for (int i = tid; i < k_teeth; i += 256) s_tooth[i] = tooth_const(i);
-  // teeth past the end repeat the last one; their results are not stored
-  // (as byte addresses of Z[k] and Z[M-k] in this frame's LDS plane)
+  // TPT > 0: LDS addresses of Z[k] and Z[M-k] in this frame's plane for the
+  // teeth j + T u; teeth past the end repeat the last one (their results are
+  // not stored)
   const char* t_za[TPT > 0 ? TPT : 1];
   const char* t_zb[TPT > 0 ? TPT : 1];
   if constexpr (TPT > 0) {
@@ -458,7 +459,7 @@ template <int LOGM, int TPT>
 int max_blocks_tt(const cg_plan* p) {
   int per_cu = 0, cus = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fft_teeth_kernel<LOGM, TPT>, 256,
-                                                   fft_lds_bytes<LOGM, TPT>(p->k)) != hipSuccess ||
+                                                   fft_lds_bytes<LOGM>(p->k)) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
           hipSuccess ||
       per_cu <= 0 || cus <= 0)
@@ -484,7 +485,7 @@ hipError_t launch_tt(const cg_plan* p, const int16_t* frames, int64_t nf, float*
   if (p->fft_blocks > 0 && blocks > p->fft_blocks) blocks = p->fft_blocks;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   if (blocks == 0) return hipSuccess;
-  fft_teeth_kernel<LOGM, TPT><<<dim3((unsigned)blocks), dim3(256), fft_lds_bytes<LOGM, TPT>(p->k),
+  fft_teeth_kernel<LOGM, TPT><<<dim3((unsigned)blocks), dim3(256), fft_lds_bytes<LOGM>(p->k),
                                  s>>>(reinterpret_cast<const int32_t*>(frames), nf, p->d_bins,
                                       p->d_half_inv_ref, reinterpret_cast<const c32*>(p->d_tw),
                                       p->k, out_mag, out_y, dev_n);
