@@ -46,6 +46,9 @@ def _run_full(plan, frames_np):
 @pytest.mark.parametrize("n,k,nf", [(512, 64, 37), (512, 128, 16), (1024, 100, 129),
                                     (2048, 220, 333), (4096, 220, 101), (8192, 440, 17),
                                     (8192, 64, 5),
+                                    # 2048-sample frames with one, two and more than
+                                    # four teeth per thread
+                                    (2048, 60, 77), (2048, 100, 45), (2048, 300, 129),
                                     # more frame groups than resident blocks, so the
                                     # persistent blocks loop, with a ragged last group
                                     (2048, 220, 20001), (1024, 200, 40001), (512, 128, 70001)])
