@@ -186,6 +186,9 @@ cg_status cg_reference_from_frames(cg_plan* plan, const int16_t* ref_frames, int
  *   out_p0      device float32[n_frames][4].
  *   out_median  device float32[n_frames][n_teeth] or NULL (then M stays on
  *               chip); must not alias y.
+ * y is taken to be finite (as normalised spectra from cg_teeth always are):
+ * the median network does not order NaNs, so a NaN in y leaves the affected
+ * filtered values and start points unspecified (never an error).
  */
 cg_status cg_init_spectra(cg_plan* plan, const float* y, int64_t n_frames, float* out_p0,
                           float* out_median, void* stream);
