@@ -273,12 +273,15 @@ constexpr int HP = MLP_HID + 8;      // LDS pitch of hidden activations (264)
 
 // One dense layer + bias + GELU for the block's 64 frames: wave w computes all
 // 64 rows of hidden units 64 w .. 64 w + 63 (4 x 4 tiles of 16 x 16).  The
-// weight fragments stream from L2 (each block reads every weight once).
+// weight fragments stream from L2 (each block reads every weight once), two
+// k-steps ahead of the products that use them, so a step waits for a load
+// issued two steps earlier rather than for a full round trip.
 template <int KDIM>
 __device__ __forceinline__ void dense_gelu64(const uint16_t* in, int pitch,
                                              const uint16_t* __restrict__ w,
                                              const float* __restrict__ bias, uint16_t* outb,
                                              int wave, int lane) {
+  constexpr int NK = KDIM / 32;
   const int fr = lane & 15, kq = (lane >> 4) * 8;
   f32x4 acc[4][4];
 #pragma unroll
@@ -286,21 +289,27 @@ __device__ __forceinline__ void dense_gelu64(const uint16_t* in, int pitch,
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const uint16_t* wrow = w + (size_t)(wave * 64 + fr) * KDIM + kq;
-#pragma unroll
-  for (int k0 = 0; k0 < KDIM; k0 += 32) {
-    u16x8 wf[4], af[4];
+  u16x8 wb[3][4];
+  auto load_w = [&](u16x8(&wf)[4], int step) __attribute__((always_inline)) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      wf[j] = *reinterpret_cast<const u16x8*>(wrow + (size_t)j * 16 * KDIM + k0);
+      wf[j] = *reinterpret_cast<const u16x8*>(wrow + (size_t)j * 16 * KDIM + step * 32);
+  };
+  load_w(wb[0], 0);
+  if constexpr (NK > 1) load_w(wb[1], 1);
+#pragma unroll
+  for (int st = 0; st < NK; ++st) {
+    if (st + 2 < NK) load_w(wb[(st + 2) % 3], st + 2);
+    u16x8 af[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      af[i] = *reinterpret_cast<const u16x8*>(in + (i * 16 + fr) * pitch + k0 + kq);
+      af[i] = *reinterpret_cast<const u16x8*>(in + (i * 16 + fr) * pitch + st * 32 + kq);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i]),
-                                                            __builtin_bit_cast(bf16x8, wf[j]),
+                                                            __builtin_bit_cast(bf16x8, wb[st % 3][j]),
                                                             acc[i][j], 0, 0, 0);
   }
   __syncthreads();  // every wave has read `in` before `outb` (may alias) is written
@@ -325,7 +334,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const uint16_t* __restrict__ w3, const float* __restrict__ b3, MlpScale sc,
     float* __restrict__ p0, const int32_t* __restrict__ dev_n) {
   // one activation buffer: each layer reads all of it before the barrier in
-  // dense_gelu64 and overwrites it after (34 KB: four blocks fit on a CU)
+  // dense_gelu64 and overwrites it after (34 KB per block)
   __shared__ __attribute__((aligned(16))) uint16_t s_x[IB * HP];
   __shared__ float s_out[IB * 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -337,35 +346,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   if (f0 >= nf) return;
   const int fr = lane & 15, kq = (lane >> 4) * 8;
 
-  // input: resample to 220 points when k != 220, round to bf16, zero pad
-  for (int idx = tid; idx < IB * MLP_IN_PAD; idx += 256) {
-    const int r = idx / MLP_IN_PAD, j = idx - r * MLP_IN_PAD;
-    int64_t f = f0 + r;
-    if (f >= nf) f = nf - 1;
-    float v = 0.f;
-    if (j < MLP_IN) {
-      if (k == MLP_IN) {
-        v = y[f * k + j];
-      } else {
+  // input: resample to 220 points when k != 220, round to bf16, zero pad.
+  // Thread tid takes the values tid + 256 m of the block's 64 x 220 inputs
+  // (row r, column j kept incrementally), eleven at a time so that their
+  // loads are in flight together; rows past the batch repeat its last frame.
+  {
+    static_assert(IB * MLP_IN % 256 == 0, "whole values per thread");
+    constexpr int NE = IB * MLP_IN / 256;  // 55
+    const int r0 = tid / MLP_IN, j0 = tid - r0 * MLP_IN;
+    const int64_t last = nf - 1;
+    auto walk = [&](auto value) __attribute__((always_inline)) {
+      int r = r0, j = j0;
+#pragma unroll 11
+      for (int m = 0; m < NE; ++m) {
+        int64_t f = f0 + r;
+        f = f < last ? f : last;
+        s_x[r * HP + j] = to_bf16(value(f, j));
+        // next value: index + 256 = (r + 1) 220 + j + 36
+        j += 256 - MLP_IN;
+        r += 1;
+        if (j >= MLP_IN) {
+          j -= MLP_IN;
+          r += 1;
+        }
+      }
+    };
+    if (k == MLP_IN) {
+      walk([&](int64_t f, int j) { return y[f * k + j]; });
+    } else {
+      walk([&](int64_t f, int j) {
         const float pos = (float)j * (float)(k - 1) / (float)(MLP_IN - 1);
         int lo = (int)floorf(pos);
         lo = lo < 0 ? 0 : (lo > k - 1 ? k - 1 : lo);
         const int hi = lo + 1 < k ? lo + 1 : k - 1;
         const float t = pos - (float)lo;
-        v = y[f * k + lo] * (1.f - t) + y[f * k + hi] * t;
-      }
+        return y[f * k + lo] * (1.f - t) + y[f * k + hi] * t;
+      });
     }
-    s_x[r * HP + j] = to_bf16(v);
+    s_x[(tid >> 2) * HP + MLP_IN + (tid & 3)] = 0;  // columns 220 .. 223
   }
   __syncthreads();
   dense_gelu64<MLP_IN_PAD>(s_x, HP, w1, b1, s_x, wave, lane);
   dense_gelu64<MLP_HID>(s_x, HP, w2, b2, s_x, wave, lane);
-  // layer 3 (256 -> 4, padded to one 16-column tile): wave w takes rows 16 w .. 16 w + 15
+  // layer 3 (256 -> 4, padded to one 16-column tile): wave w takes rows 16 w .. 16 w + 15;
+  // its eight weight fragments are loaded together
   {
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    u16x8 w3f[MLP_HID / 32];
+#pragma unroll
+    for (int st = 0; st < MLP_HID / 32; ++st)
+      w3f[st] = *reinterpret_cast<const u16x8*>(w3 + (size_t)fr * MLP_HID + st * 32 + kq);
 #pragma unroll
     for (int k0 = 0; k0 < MLP_HID; k0 += 32) {
-      const u16x8 wf = *reinterpret_cast<const u16x8*>(w3 + (size_t)fr * MLP_HID + k0 + kq);
+      const u16x8 wf = w3f[k0 / 32];
       const u16x8 af = *reinterpret_cast<const u16x8*>(s_x + (wave * 16 + fr) * HP + k0 + kq);
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af),
                                                     __builtin_bit_cast(bf16x8, wf), acc, 0, 0, 0);
