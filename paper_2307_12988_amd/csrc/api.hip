@@ -305,7 +305,7 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
     e = cg::launch_mlp_infer(p->mlp, y, nf, p->k, p0, s);
     if (e == hipSuccess)
       e = cg::launch_lm(y, p0, nf, p->k, p->polish_iters, out_params, out_iters, out_status,
-                        chi2, s, p->lm_chunk);
+                        chi2, s, p->lm_chunk, nullptr, fb_count);
     if (e == hipSuccess)
       e = cg::launch_fallback_select(chi2, nf, p->k, p->mlp->noise_floor, fb_flags, fb_idx,
                                      fb_count, s);

@@ -82,9 +82,12 @@ hipError_t launch_start_points(const float* m, int64_t n_frames, int k, float* o
 // (<= 0: chosen from n_frames and the tooth count).
 int lm_group(int n_teeth);
 int lm_chunk(int64_t n_frames, int n_teeth);
+// zero_count, if not null, is set to 0 by the kernel (for a counter the next
+// kernel on the stream accumulates into).
 hipError_t launch_lm(const float* y, const float* p0, int64_t n_frames, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
-                     int chunk = 0, const int32_t* dev_n = nullptr);
+                     int chunk = 0, const int32_t* dev_n = nullptr,
+                     int32_t* zero_count = nullptr);
 // Indexed form: fit frames idx[0..*count) (count read on the device, at most
 // n_cap); every reported status is replaced by status_code.
 hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx,
@@ -92,7 +95,8 @@ hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx
                              float* params, int32_t* iters, int32_t* status, float* chi2,
                              int32_t status_code, hipStream_t s);
 // Warm-start fallback selection: flags[f] = 1 and f appended to idx when the
-// polished fit's RMS residual exceeds 2 * noise_floor or is not finite.
+// polished fit's RMS residual exceeds 2 * noise_floor or is not finite.  The
+// count accumulates: it must be zero on entry (the polish launch clears it).
 hipError_t launch_fallback_select(const float* chi2, int64_t n_frames, int k, float noise_floor,
                                   int32_t* flags, int32_t* idx, int32_t* count, hipStream_t s,
                                   const int32_t* dev_n = nullptr);

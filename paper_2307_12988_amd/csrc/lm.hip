@@ -231,8 +231,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                                  float* __restrict__ params,
                                                  int32_t* __restrict__ iters,
                                                  int32_t* __restrict__ status,
-                                                 float* __restrict__ chi2_out, int status_code) {
+                                                 float* __restrict__ chi2_out, int status_code,
+                                                 int32_t* __restrict__ zero_count) {
   constexpr int NG = 64 / G;  // spectra in flight per wave
+  // a counter the next kernel on the stream accumulates into (the fallback
+  // list after a polish), cleared here so that no kernel has to do only that
+  if (zero_count && blockIdx.x == 0 && threadIdx.x == 0) *zero_count = 0;
   const int lane = lane_id();
   const int grp = lane / G;
   const int gl = lane & (G - 1);
@@ -342,29 +346,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 }
 
 
-// One block lists the fallback frames: every thread scans a strided share of
-// the batch and appends through a counter in LDS, and the count is written
-// once at the end, so no separate kernel has to clear a global counter first
-// (the list order is not specified).
-__global__ __launch_bounds__(1024) void fallback_select_kernel(
+// The fallback list, one block per 1024 frames: a block flags its frames,
+// counts them with a block-wide scan and reserves its place in the list with
+// one atomic add on the count, which the polish fit (the kernel before this
+// one on the stream) has cleared.  The list order is not specified.
+constexpr int FB_THREADS = 256, FB_PER = 4;
+__global__ __launch_bounds__(FB_THREADS) void fallback_select_kernel(
     const float* __restrict__ chi2, int64_t nf, float thr2, int32_t* __restrict__ flags,
     int32_t* __restrict__ idx, int32_t* __restrict__ count, const int32_t* __restrict__ dev_n) {
-  __shared__ int32_t s_count;
+  __shared__ int32_t s_wave[FB_THREADS / 64];
+  __shared__ int32_t s_base;
   if (dev_n) {
     const int64_t dn = *dev_n;
     nf = dn < nf ? dn : nf;
   }
-  if (threadIdx.x == 0) s_count = 0;
+  const int64_t f0 = (int64_t)blockIdx.x * FB_THREADS * FB_PER;
+  if (f0 >= nf) return;  // uniform over the block
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  uint32_t mask = 0;
+#pragma unroll
+  for (int i = 0; i < FB_PER; ++i) {
+    const int64_t f = f0 + t + (int64_t)FB_THREADS * i;
+    if (f < nf) {
+      // RMS residual sqrt(chi2 / (k - 4)) > 2 sigma  <=>  chi2 > 4 sigma^2 (k - 4)
+      const float c = chi2[f];
+      const bool bad = !isfinite(c) || c > thr2;
+      flags[f] = bad ? 1 : 0;
+      mask |= (uint32_t)bad << i;
+    }
+  }
+  const int cnt = __popc(mask);
+  int incl = cnt;  // inclusive scan over the wave
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int v = __shfl_up(incl, d);
+    incl += lane >= d ? v : 0;
+  }
+  if (lane == 63) s_wave[wv] = incl;
   __syncthreads();
-  for (int64_t f = threadIdx.x; f < nf; f += blockDim.x) {
-    // RMS residual sqrt(chi2 / (k - 4)) > 2 sigma  <=>  chi2 > 4 sigma^2 (k - 4)
-    const float c = chi2[f];
-    const bool bad = !isfinite(c) || c > thr2;
-    flags[f] = bad ? 1 : 0;
-    if (bad) idx[atomicAdd(&s_count, 1)] = (int32_t)f;
+  if (t == 0) {
+    int total = 0;
+#pragma unroll
+    for (int w = 0; w < FB_THREADS / 64; ++w) total += s_wave[w];
+    s_base = total > 0 ? atomicAdd(count, total) : 0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) *count = s_count;
+  int off = s_base + incl - cnt;
+#pragma unroll
+  for (int w = 0; w < FB_THREADS / 64; ++w) off += w < wv ? s_wave[w] : 0;
+  while (mask) {
+    const int i = __builtin_ffs(mask) - 1;
+    mask &= mask - 1;
+    idx[off++] = (int32_t)(f0 + t + (int64_t)FB_THREADS * i);
+  }
 }
 
 }  // namespace
@@ -375,8 +409,10 @@ hipError_t launch_fallback_select(const float* chi2, int64_t nf, int k, float no
   if (nf > 0x7fffffff) return hipErrorInvalidValue;
   const double dof = k > 4 ? (double)(k - 4) : 1.0;
   const float thr2 = (float)(4.0 * (double)noise_floor * (double)noise_floor * dof);
-  hipLaunchKernelGGL(fallback_select_kernel, dim3(1), dim3(1024), 0, s, chi2, nf, thr2, flags,
-                     idx, count, dev_n);
+  const int64_t blocks = (nf + FB_THREADS * FB_PER - 1) / (FB_THREADS * FB_PER);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(fallback_select_kernel, dim3((unsigned)blocks), dim3(FB_THREADS), 0, s, chi2,
+                     nf, thr2, flags, idx, count, dev_n);
   return hipGetLastError();
 }
 
@@ -403,12 +439,13 @@ template <int G, int Q>
 hipError_t launch_lm_gq(const float* y, const float* p0, const int32_t* idx,
                         const int32_t* count, int64_t nf, int k, int max_iter, int chunk,
                         float* params, int32_t* iters, int32_t* status, float* chi2,
-                        int32_t status_code, hipStream_t s) {
+                        int32_t status_code, int32_t* zero_count, hipStream_t s) {
   const int64_t waves = (nf + chunk - 1) / chunk;
   const int64_t blocks = (waves + 3) / 4;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL((lm_kernel<G, Q>), dim3((unsigned)blocks), dim3(256), 0, s, y, p0, idx,
-                     count, nf, k, max_iter, chunk, params, iters, status, chi2, status_code);
+                     count, nf, k, max_iter, chunk, params, iters, status, chi2, status_code,
+                     zero_count);
   return hipGetLastError();
 }
 
@@ -418,11 +455,11 @@ template <int G>
 hipError_t launch_lm_g(const float* y, const float* p0, const int32_t* idx,
                        const int32_t* count, int64_t nf, int k, int max_iter, int chunk,
                        float* params, int32_t* iters, int32_t* status, float* chi2,
-                       int32_t status_code, hipStream_t s) {
+                       int32_t status_code, int32_t* zero_count, hipStream_t s) {
 #define CG_LM_CASE(QV)                                                                   \
   case QV:                                                                               \
     return launch_lm_gq<G, QV>(y, p0, idx, count, nf, k, max_iter, chunk, params, iters, \
-                               status, chi2, status_code, s);
+                               status, chi2, status_code, zero_count, s);
   switch ((k + G - 1) / G) {
     CG_LM_CASE(1) CG_LM_CASE(2) CG_LM_CASE(3) CG_LM_CASE(4) CG_LM_CASE(5) CG_LM_CASE(6)
     CG_LM_CASE(7) CG_LM_CASE(8) CG_LM_CASE(9) CG_LM_CASE(10) CG_LM_CASE(11) CG_LM_CASE(12)
@@ -439,23 +476,23 @@ hipError_t launch_lm_g(const float* y, const float* p0, const int32_t* idx,
 hipError_t launch_lm_any(const float* y, const float* p0, const int32_t* idx,
                          const int32_t* count, int64_t nf, int k, int max_iter, int chunk,
                          float* params, int32_t* iters, int32_t* status, float* chi2,
-                         int32_t status_code, hipStream_t s) {
+                         int32_t status_code, int32_t* zero_count, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   if (lm_group(k) == 8)
     return launch_lm_g<8>(y, p0, idx, count, nf, k, max_iter, chunk, params, iters, status,
-                          chi2, status_code, s);
+                          chi2, status_code, zero_count, s);
   return launch_lm_g<16>(y, p0, idx, count, nf, k, max_iter, chunk, params, iters, status,
-                         chi2, status_code, s);
+                         chi2, status_code, zero_count, s);
 }
 
 }  // namespace
 
 hipError_t launch_lm(const float* y, const float* p0, int64_t nf, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
-                     int chunk, const int32_t* dev_n) {
+                     int chunk, const int32_t* dev_n, int32_t* zero_count) {
   if (chunk <= 0) chunk = lm_chunk(nf, k);
   return launch_lm_any(y, p0, nullptr, dev_n, nf, k, max_iter, chunk, params, iters, status,
-                       chi2, -1, s);
+                       chi2, -1, zero_count, s);
 }
 
 hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx,
@@ -465,7 +502,7 @@ hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx
   // the count is only known on the device: one spectrum per group keeps waves busy
   const int chunk = 64 / lm_group(k);
   return launch_lm_any(y, p0, idx, count, n_cap, k, max_iter, chunk, params, iters, status,
-                       chi2, status_code, s);
+                       chi2, status_code, nullptr, s);
 }
 
 }  // namespace cg

@@ -156,7 +156,7 @@ hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
     if (le == hipSuccess) le = launch_mlp_infer(p->mlp, sl.y, cap, p->k, sl.p0, s, sl.n_dev);
     if (le == hipSuccess)
       le = launch_lm(sl.y, sl.p0, cap, p->k, p->polish_iters, sl.params, sl.iters, sl.status,
-                     sl.chi2, s, p->lm_chunk, sl.n_dev);
+                     sl.chi2, s, p->lm_chunk, sl.n_dev, sl.fb_count);
     if (le == hipSuccess)
       le = launch_fallback_select(sl.chi2, cap, p->k, p->mlp->noise_floor, sl.fb_flags, sl.fb_idx,
                                   sl.fb_count, s, sl.n_dev);
