@@ -69,7 +69,8 @@ hipError_t launch_column_mean(const float* mags, int64_t n, int k, float* out, h
 
 // A4: 7x7 median image (out_m, may be null) and/or start points (out_p0, may
 // be null) from normalised spectra, in one kernel.
-// flags (may be null): only frames with flags[f] != 0 get a start point, and
+// flags (may be null): only frames with flags[f] != 0 get a start point (and
+// a filtered row in out_m; rows of other frames are left unwritten), and
 // blocks without such frames return at once.
 hipError_t launch_median_start(const float* y, int64_t n_frames, int k, float* out_m,
                                float* out_p0, hipStream_t s, const int32_t* flags = nullptr,
