@@ -158,10 +158,14 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
   const int besti = (int)(uint32_t)best;
   const float bestv = key_float((uint32_t)(best >> 32));
 
-  // Lower median (order statistic r = (k-1)/2) by bisection over the key
-  // interval [lo, hi], which always holds the answer; c_lo = #{keys < lo},
-  // c_hi = #{keys <= hi}.  When the interval holds a single key the answer is
-  // the smallest key >= lo.
+  // Lower median (order statistic r = (k-1)/2).  The key interval [lo, hi]
+  // always holds it, with c_lo = #{keys < lo} <= r < c_hi = #{keys <= hi};
+  // every probe lies in (lo, hi], so the choice of probes changes only how
+  // fast the interval shrinks, never the result.  A gallop from a guess and
+  // then bisection shrink it until at most four keys lie in it; the
+  // remaining keys are then taken in order, smallest first, until the count
+  // passes r.  (Near the median the keys are dense, so isolating a single
+  // key by bisection takes several more probes than reading the last few.)
   const int r = (k - 1) / 2;
   uint32_t lo = (uint32_t)(best >> 32), hi = 0u;
 #pragma unroll
@@ -175,7 +179,55 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
 #pragma unroll
   for (int q = 0; q < Q; ++q) keys[q] = gl + 16 * q < k ? keys[q] : 0xffffffffu;
   int c_lo = 0, c_hi = k;
-  while (lo < hi && c_hi - c_lo > 1) {
+  if (lo < hi && c_hi - c_lo > 4) {
+    // Gallop from a guess, the mean of the values at or above the row mean
+    // (the dip pulls the plain mean below the baseline), in steps that double
+    // until they leave [lo, hi]; this skips most of the probes that bisection
+    // from [min, max] spends outside the baseline cluster.
+    float sm = 0.0f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sm += gl + 16 * q < k ? mv[q] : 0.0f;
+    sm = sum16(sm);
+    const float mean = sm * __builtin_amdgcn_rcpf((float)k);
+    float su = 0.0f;
+    int nu = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const bool up = gl + 16 * q < k && mv[q] >= mean;
+      su += up ? mv[q] : 0.0f;
+      nu += up ? 1 : 0;
+    }
+    su = sum16(su);  // bit-identical in the 16 lanes, so the probes are too
+    nu = sum16(nu);
+    uint32_t mid = float_key(su * __builtin_amdgcn_rcpf((float)(nu > 0 ? nu : 1)) + 0.0f);
+    mid = mid <= lo ? lo + 1u : (mid > hi ? hi : mid);
+    uint32_t step = (hi - lo) >> 8;
+    step = step > 0u ? step : 1u;
+    for (int p = 0; p < 10 && c_hi - c_lo > 4; ++p) {
+      uint32_t ca = 0, cb = 0;
+#pragma unroll
+      for (int q = 0; q + 1 < Q; q += 2) {
+        ca += (uint32_t)(keys[q] < mid);
+        cb += (uint32_t)(keys[q + 1] < mid);
+        asm volatile("" : "+v"(ca), "+v"(cb));
+      }
+      if constexpr (Q % 2 == 1) ca += (uint32_t)(keys[Q - 1] < mid);
+      const int c = sum16((int)(ca + cb));
+      if (c <= r) {
+        lo = mid;
+        c_lo = c;
+        if (hi - mid < step) break;
+        mid += step;  // still <= hi
+      } else {
+        hi = mid - 1u;
+        c_hi = c;
+        if (mid - lo <= step) break;
+        mid -= step;  // still > lo
+      }
+      step = step < 0x40000000u ? step << 1 : step;
+    }
+  }
+  while (lo < hi && c_hi - c_lo > 4) {
     const uint32_t mid = lo + ((hi - lo) >> 1) + 1u;  // lo < mid <= hi
     // One compare and one add with carry per key, in two interleaved
     // chains; the empty asm keeps the compiler from packing the comparisons
@@ -198,11 +250,34 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
     }
   }
   if (lo < hi) {
-    uint32_t m = 0xffffffffu;
+    // Each round finds the smallest key m >= cur (keys below cur wrap to
+    // large differences) and counts the keys in [cur, m]; the answer is the
+    // first m at which the count passes r.  At most four distinct keys
+    // remain, so at most four rounds.
+    uint32_t cur = lo, m = lo;
+    int c = c_lo;
+    for (int e = 0; e < 4; ++e) {
+      uint32_t dmin = 0xffffffffu;
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-      if (keys[q] >= lo && keys[q] < m) m = keys[q];
-    lo = min16(m);
+      for (int q = 0; q < Q; ++q) {
+        const uint32_t dq = keys[q] - cur;
+        dmin = dq < dmin ? dq : dmin;
+      }
+      dmin = min16(dmin);
+      m = cur + dmin;
+      uint32_t ca = 0, cb = 0;
+#pragma unroll
+      for (int q = 0; q + 1 < Q; q += 2) {
+        ca += (uint32_t)(keys[q] - cur <= dmin);
+        cb += (uint32_t)(keys[q + 1] - cur <= dmin);
+        asm volatile("" : "+v"(ca), "+v"(cb));
+      }
+      if constexpr (Q % 2 == 1) ca += (uint32_t)(keys[Q - 1] - cur <= dmin);
+      c += sum16((int)(ca + cb));
+      if (c > r) break;
+      cur = m + 1u;
+    }
+    lo = m;
   }
   const uint32_t prefix = lo;
   const float med = key_float(prefix);
