@@ -37,12 +37,12 @@ HBM_PEAK_GBS = 8000.0
 VALU_FP32_PEAK_TFLOPS = 157.3
 VALU_FP64_PEAK_TFLOPS = 78.6
 VALU_OPS_PEAK_TOPS = 78.6
-# min/max operations per filtered value: four windows per step share merged
-# row pairs (4 row sorts of 16 compare-exchanges, 2 pair merges of 42, a
-# 100-op common merge, 2 x 72 shared-set merges, 4 x 14 final merges per four
-# values: 128), plus each 16-frame block's start-up (6 row sorts and 2 pair
-# merges: 276 per 16 values)
-MEDIAN_OPS_PER_OUTPUT = 128 + 276 / 16
+# min/max/med3 operations per filtered value as the network generator emits
+# them: four windows per step share merged row pairs (4 row sorts of 27, 2
+# pair merges of 42, a 98-op common merge, 2 x 61 shared-set merges, 4 x 13
+# final merges per four values: 116), plus each 16-frame block's start-up
+# (6 row sorts and 2 pair merges: 246 per 16 values)
+MEDIAN_OPS_PER_OUTPUT = 116 + 246 / 16
 SEED = 1
 
 # HBM bytes per launch of the paper-rate workload from rocprofv3 FETCH_SIZE and

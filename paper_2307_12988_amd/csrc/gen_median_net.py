@@ -21,15 +21,31 @@ t..t+6, t+1..t+7, t+2..t+8 and t+3..t+9.  With L1..L4 the merged row pairs
 * L3 and L4 of one step are L1 and L2 of the next (t + 4), so each step merges
   two new row pairs (CG_MERGE77) and sorts four new rows.
 
-Per output that is 4 x 32 (row sorts) + 2 x 42 + 100 + 2 x 72 + 4 x 14 = 512
-min/max operations per four outputs, 128 per output.
-
 All merges are Batcher odd-even merges (lists padded to a power of two with
 +inf) pruned symbolically to the outputs needed; comparisons against a
 constant +inf vanish and only the min or max side of a comparator that is
-used is emitted.  CG_SORT7 is the 16-comparator 7-input sorting network.  The
-script checks the composed networks against numpy's median on random inputs
-with ties before writing the file.
+used is emitted.
+
+The hardware has three-input min, max and median instructions at the rate of
+the two-input ones, so two further rewrites pay:
+* CG_SORT7 sorts three values with one min3, med3 and max3 and then inserts
+  the other four one at a time; inserting x into a sorted list s gives
+  min(x, s0), med3(s(j-1), x, s(j)) for the inner positions and
+  max(x, s_last): 25 operations instead of the 32 of the best two-input
+  network (16 comparators).
+* In a pruned merge, max(min(a, b), c) equals med3(a, b, c) whenever c <= a
+  or c <= b holds for every input, and min(max(a, b), c) does whenever
+  a <= c or b <= c does; where the inner operation has no other use the two
+  become one.  The conditions are proved by the 0-1 principle (every node is
+  a monotone function of the inputs, so an order that holds on all 0-1
+  inputs with sorted lists holds on all inputs).
+The compiler fuses min(min(a, b), c) and max(max(...)) by itself.  Before
+the rewrites a step took 4 x 32 (row sorts) + 2 x 42 + 100 + 2 x 72 + 4 x 14
+= 512 min/max operations per four outputs (128 per output).
+
+The script checks every network exhaustively on 0-1 inputs and the composed
+networks against numpy's median on random inputs with ties before writing
+the file.
 """
 
 import os
@@ -37,18 +53,7 @@ import sys
 
 import numpy as np
 
-SORT7 = [(0, 6), (2, 3), (4, 5), (0, 2), (1, 4), (3, 6), (0, 1), (2, 5), (3, 4),
-         (1, 2), (4, 6), (2, 3), (4, 5), (1, 2), (3, 4), (5, 6)]
 INF = -1
-
-
-def _check_sort7():
-    for bits in range(128):
-        v = [(bits >> i) & 1 for i in range(7)]
-        for a, b in SORT7:
-            if v[a] > v[b]:
-                v[a], v[b] = v[b], v[a]
-        assert v == sorted(v), bits
 
 
 def _oe_merge(w):
@@ -112,21 +117,104 @@ def merge_select(list_lens, want_ranks):
     return kept, outs
 
 
+def _apply(op, x):
+    if op == "min":
+        return np.minimum(x[0], x[1])
+    if op == "max":
+        return np.maximum(x[0], x[1])
+    lo, hi = np.minimum(x[0], x[1]), np.maximum(x[0], x[1])  # med3
+    return np.maximum(lo, np.minimum(hi, x[2]))
+
+
 def evaluate(kept, outs, vals):
     env = {i: vals[:, i] for i in range(vals.shape[1])}
-    for nid, op, a, b in kept:
-        env[nid] = np.minimum(env[a], env[b]) if op == "min" else np.maximum(env[a], env[b])
+    for nid, op, *args in kept:
+        env[nid] = _apply(op, [env[a] for a in args])
     return np.stack([env[o] for o in outs], axis=1)
 
 
-def emit(name, kept, outs, n_in, in_name="IN", out_name="OUT"):
-    lines = [f"// {name}: {len(kept)} min/max operations",
-             f"#define {name}({in_name}, {out_name}) do {{ \\"]
+def zero_one_inputs(list_lens):
+    """Every 0-1 input whose lists are each sorted ascending."""
+    rows = []
+    for zeros in np.ndindex(*[n + 1 for n in list_lens]):
+        v = []
+        for n, z in zip(list_lens, zeros):
+            v += [0] * z + [1] * (n - z)
+        rows.append(v)
+    return np.array(rows, dtype=np.int8)
+
+
+def fuse_med3(kept, outs, list_lens):
+    """Replace max(min(a, b), c) by med3(a, b, c) where c <= a or c <= b on
+    every sorted 0-1 input (and min(max(a, b), c) where a <= c or b <= c),
+    when the inner operation has no other use."""
+    n_in = sum(list_lens)
+    zo = zero_one_inputs(list_lens)
+    env = {i: zo[:, i] for i in range(n_in)}
+    node = {}
+    uses = {}
     for nid, op, a, b in kept:
-        sa = f"{in_name}[{a}]" if a < n_in else f"_t{a}"
-        sb = f"{in_name}[{b}]" if b < n_in else f"_t{b}"
-        fn = "fminf" if op == "min" else "fmaxf"
-        lines.append(f"  const float _t{nid} = {fn}({sa}, {sb}); \\")
+        env[nid] = _apply(op, [env[a], env[b]])
+        node[nid] = (op, a, b)
+        uses[a] = uses.get(a, 0) + 1
+        uses[b] = uses.get(b, 0) + 1
+    for o in outs:
+        uses[o] = uses.get(o, 0) + 1
+
+    def le(x, y):
+        return bool(np.all(env[x] <= env[y]))
+
+    dead = set()
+    new = {}
+    for nid, op, a, b in kept:
+        for p, c in ((a, b), (b, a)):
+            if p not in node or p in dead or uses[p] != 1 or p in new:
+                continue
+            pop, pa, pb = node[p]
+            if (op == "max" and pop == "min" and (le(c, pa) or le(c, pb))) or \
+               (op == "min" and pop == "max" and (le(pa, c) or le(pb, c))):
+                dead.add(p)
+                new[nid] = (nid, "med3", pa, pb, c)
+                break
+    return [new.get(t[0], t) for t in kept if t[0] not in dead]
+
+
+def check_zero_one(kept, outs, list_lens, want_ranks):
+    """Exhaustive 0-1 check: the outputs are the wanted ranks of the merge."""
+    zo = zero_one_inputs(list_lens)
+    got = evaluate(kept, outs, zo)
+    want = np.sort(zo, axis=1)[:, want_ranks]
+    assert np.array_equal(got, want)
+
+
+def sort7_ops():
+    """Sort of V[0..6] (inputs 0..6) as SSA operations: min3/med3/max3 of the
+    first three, then insertion of V[3] .. V[6]."""
+    ops = []
+    nid = [7]
+
+    def put(op, *args):
+        ops.append((nid[0], op) + args)
+        nid[0] += 1
+        return nid[0] - 1
+
+    m = put("min", 0, 1)
+    s = [put("min", m, 2), put("med3", 0, 1, 2), put("max", put("max", 0, 1), 2)]
+    for x in range(3, 7):
+        t = [put("min", x, s[0])]
+        t += [put("med3", s[j - 1], x, s[j]) for j in range(1, len(s))]
+        t.append(put("max", x, s[-1]))
+        s = t
+    return ops, s
+
+
+def emit(name, kept, outs, n_in, in_name="IN", out_name="OUT"):
+    lines = [f"// {name}: {len(kept)} min/max/med3 operations",
+             f"#define {name}({in_name}, {out_name}) do {{ \\"]
+    fns = {"min": "fminf", "max": "fmaxf", "med3": "__builtin_amdgcn_fmed3f"}
+    for nid, op, *args in kept:
+        srcs = ", ".join(f"{in_name}[{a}]" if a < n_in else f"_t{a}" for a in args)
+        lines.append(f"  const float _t{nid} = {fns[op]}({srcs}); \\")
     for j, o in enumerate(outs):
         src = f"{in_name}[{o}]" if o < n_in else f"_t{o}"
         lines.append(f"  {out_name}[{j}] = {src}; \\")
@@ -135,26 +223,35 @@ def emit(name, kept, outs, n_in, in_name="IN", out_name="OUT"):
 
 
 def emit_sort7(name):
-    lines = [f"// {name}: 16 compare-exchanges, sorts V[0..6] ascending",
-             f"#define {name}(V) do {{ \\"]
-    for a, b in SORT7:
-        lines.append(f"  {{ const float _lo = fminf(V[{a}], V[{b}]); "
-                     f"V[{b}] = fmaxf(V[{a}], V[{b}]); V[{a}] = _lo; }} \\")
-    lines.append("} while (0)")
-    return "\n".join(lines) + "\n"
+    ops, outs = sort7_ops()
+    # in place: the outputs overwrite the inputs only after every temporary
+    # is formed
+    text = emit(name, ops, outs, 7, "V", "V")
+    text = text.replace(f"#define {name}(V, V)", f"#define {name}(V)", 1)
+    return text.replace(f"// {name}: ", f"// {name}: sorts V[0..6] ascending in place, ", 1)
 
 
 def main(path):
-    _check_sort7()
-    k77, o77 = merge_select([7, 7], list(range(14)))
-    kc, oc = merge_select([14, 14], list(range(3, 25)))
-    kp, op = merge_select([22, 14], list(range(14, 22)))
-    kf, of = merge_select([8, 7], [7])
+    s7, s7o = sort7_ops()
+    zo = np.array([[(bits >> i) & 1 for i in range(7)] for bits in range(128)], dtype=np.int8)
+    assert np.array_equal(evaluate(s7, s7o, zo), np.sort(zo, axis=1))
+    nets = {}
+    for name, lens, ranks in (("k77", [7, 7], list(range(14))),
+                              ("kc", [14, 14], list(range(3, 25))),
+                              ("kp", [22, 14], list(range(14, 22))),
+                              ("kf", [8, 7], [7])):
+        kept, outs = merge_select(lens, ranks)
+        kept = fuse_med3(kept, outs, lens)
+        check_zero_one(kept, outs, lens, ranks)
+        nets[name] = (kept, outs)
+    (k77, o77), (kc, oc), (kp, op), (kf, of) = nets["k77"], nets["kc"], nets["kp"], nets["kf"]
     rng = np.random.default_rng(0)
     for trial in range(4):
         v = rng.random((20000, 70)) if trial % 2 == 0 else \
             rng.integers(0, 5, size=(20000, 70)).astype(np.float64)
-        rows = np.sort(v.reshape(-1, 10, 7), axis=2)  # rows t .. t+9, each sorted
+        raw = v.reshape(-1, 10, 7)
+        rows = np.stack([evaluate(s7, s7o, raw[:, j]) for j in range(10)], axis=1)
+        assert np.array_equal(rows, np.sort(raw, axis=2))  # rows t .. t+9, each sorted
         lists = [evaluate(k77, o77, np.concatenate([rows[:, 2 * j + 1], rows[:, 2 * j + 2]],
                                                    axis=1)) for j in range(4)]
         core = evaluate(kc, oc, np.concatenate([lists[1], lists[2]], axis=1))

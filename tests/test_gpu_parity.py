@@ -136,6 +136,24 @@ def test_init_bit_exact_with_repeated_and_signed_values(levels):
     assert np.array_equal(p0.cpu().numpy(), oracle.initial_guess(y))
 
 
+@pytest.mark.parametrize("k", [9, 220, 440])
+def test_init_bit_exact_with_values_across_many_exponents(k):
+    """Magnitudes from 1e-30 to 1e30 of either sign and a subnormal row: the
+    selection's probes span almost the whole key range, where its doubling
+    steps are largest."""
+    _say(f"init wide range k={k}")
+    rng = np.random.default_rng(300 + k)
+    nf = 80
+    y = (10.0 ** rng.uniform(-30, 30, (nf, k))).astype(np.float32)
+    y *= np.where(rng.random((nf, k)) < 0.3, -1.0, 1.0).astype(np.float32)
+    y[7] = np.float32(1e-45)  # subnormal
+    plan = cg.Plan(2048, 1e9, np.arange(1, k + 1), np.ones(k))
+    p0, med = plan.init_spectra(torch.from_numpy(y).to(DEV), want_median=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(med.cpu().numpy(), oracle.median7x7(y))
+    assert np.array_equal(p0.cpu().numpy(), oracle.initial_guess(y))
+
+
 def test_median_filter_and_start_points_separately():
     rng = np.random.default_rng(8)
     nf, k = 45, 220
