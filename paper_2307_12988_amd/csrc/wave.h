@@ -125,7 +125,8 @@ __device__ __forceinline__ uint32_t max16(uint32_t v) {
 // Order-preserving map of float bits to unsigned (negatives below positives).
 __device__ __forceinline__ uint32_t float_key(float f) {
   const uint32_t u = __float_as_uint(f);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  // negatives: all bits flipped; others: the sign bit set
+  return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
 }
 __device__ __forceinline__ float key_float(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
@@ -134,9 +135,12 @@ __device__ __forceinline__ float key_float(uint32_t k) {
 // ---------------------------------------------------------------------------
 // Start point of the Lorentzian fit from one row of the 7x7-median image,
 // computed by a group of 16 lanes.  Lane gl of the group holds row values
-// i = gl + 16 q (q < Q), masked beyond k.
+// i = gl + 16 q (q < Q); slots with i >= k must hold a copy of a value of
+// the row (the callers repeat the last tooth), so that the minimum, maximum
+// and guess need no mask: a copy never beats its original, whose index is
+// smaller.
 //   c0 = first index of the minimum; b0 = lower median (order statistic
-//   (k-1)/2, by bisection over order-preserving keys);
+//   (k-1)/2, found by counting over order-preserving keys);
 //   d0 = clip(1 - M[c0]/b0, 0.05, 0.95), 0.05 if b0 <= 0;
 //   w0 = max(2, #{M < b0 (1 - d0/2)}).
 // The arithmetic that decides d0 and the count uses IEEE float32 operations in
@@ -145,16 +149,17 @@ template <int Q>
 __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float& c0, float& w0,
                                               float& d0, float& b0) {
   const int gl = lane_id() & 15;
-  uint64_t best = ~0ull;
   uint32_t keys[Q];
+  // the lane's first minimum (slots in increasing index), then the group's
+  uint32_t bk = 0xffffffffu, bi = 0u;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int i = gl + 16 * q;
     keys[q] = float_key(mv[q] + 0.0f);  // -0 -> +0: equal values, equal keys
-    const uint64_t cand = ((uint64_t)keys[q] << 32) | (uint32_t)i;
-    if (i < k && cand < best) best = cand;
+    const bool lt = keys[q] < bk || q == 0;
+    bk = lt ? keys[q] : bk;
+    bi = lt ? (uint32_t)(gl + 16 * q) : bi;
   }
-  best = min16(best);
+  const uint64_t best = min16(((uint64_t)bk << 32) | bi);
   const int besti = (int)(uint32_t)best;
   const float bestv = key_float((uint32_t)(best >> 32));
 
@@ -169,10 +174,7 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
   const int r = (k - 1) / 2;
   uint32_t lo = (uint32_t)(best >> 32), hi = 0u;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int i = gl + 16 * q;
-    if (i < k) hi = keys[q] > hi ? keys[q] : hi;
-  }
+  for (int q = 0; q < Q; ++q) hi = keys[q] > hi ? keys[q] : hi;
   hi = max16(hi);
   // Teeth past the end take the largest key: no key is below it and no
   // probe above it, so they never count and the counts need no mask.
@@ -184,16 +186,17 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
     // (the dip pulls the plain mean below the baseline), in steps that double
     // until they leave [lo, hi]; this skips most of the probes that bisection
     // from [min, max] spends outside the baseline cluster.
+    // (the repeated last tooth takes part: it moves the guess, not the result)
     float sm = 0.0f;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) sm += gl + 16 * q < k ? mv[q] : 0.0f;
+    for (int q = 0; q < Q; ++q) sm += mv[q];
     sm = sum16(sm);
-    const float mean = sm * __builtin_amdgcn_rcpf((float)k);
+    const float mean = sm * (1.0f / (16 * Q));
     float su = 0.0f;
     int nu = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const bool up = gl + 16 * q < k && mv[q] >= mean;
+      const bool up = mv[q] >= mean;
       su += up ? mv[q] : 0.0f;
       nu += up ? 1 : 0;
     }
@@ -289,13 +292,18 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
     d = 0.05f;
   }
   const float thr = __fmul_rn(med, __fsub_rn(1.0f, __fmul_rn(d, 0.5f)));
-  int cnt = 0;
+  // M < thr compared as keys (the same order for non-NaN values; the slots
+  // past the end carry the largest key and never count)
+  const uint32_t tk = float_key(thr + 0.0f);
+  uint32_t ca = 0, cb = 0;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int i = gl + 16 * q;
-    cnt += (i < k) && (mv[q] < thr);
+  for (int q = 0; q + 1 < Q; q += 2) {
+    ca += (uint32_t)(keys[q] < tk);
+    cb += (uint32_t)(keys[q + 1] < tk);
+    asm volatile("" : "+v"(ca), "+v"(cb));
   }
-  cnt = sum16(cnt);
+  if constexpr (Q % 2 == 1) ca += (uint32_t)(keys[Q - 1] < tk);
+  const int cnt = sum16((int)(ca + cb));
   c0 = (float)besti;
   w0 = (float)(cnt > 2 ? cnt : 2);
   d0 = d;
