@@ -103,14 +103,15 @@ __device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, double c, 
   for (int q = 0; q < Q; ++q) {
     // The empty asm statements pin pairs of slots in program order: the u of
     // the pair's first slot passes through one before the pair's arithmetic
-    // (the second slot's u is derived from it) and the sums pass through one
-    // after the pair.  Left alone, the compiler evaluates the FP64 part of
+    // and the sums pass through one after the pair.  Each u is the previous
+    // one plus the tooth step (one FP64 add; an fma from u0 with the slot's
+    // offset needs a register copy of u0 first, as the offset is a literal).  Left alone, the compiler evaluates the FP64 part of
     // every slot first and keeps all of it live (about 100 extra VGPRs); two
     // slots at a time give the scheduler two independent chains.
     const int i = gl + G * q;
     double u;
     if (q % 2 == 0) {
-      u = fma((double)(G * q), two_iw, u0);
+      u = q == 0 ? u0 : u_prev + step;
       asm volatile("" : "+v"(u));
     } else {
       u = u_prev + step;
