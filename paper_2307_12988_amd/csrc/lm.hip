@@ -500,10 +500,14 @@ hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx
                              const int32_t* count, int64_t n_cap, int k, int max_iter,
                              float* params, int32_t* iters, int32_t* status, float* chi2,
                              int32_t status_code, hipStream_t s) {
-  // the count is only known on the device: one spectrum per group keeps waves busy
-  const int chunk = 64 / lm_group(k);
-  return launch_lm_any(y, p0, idx, count, n_cap, k, max_iter, chunk, params, iters, status,
-                       chi2, status_code, nullptr, s);
+  // The count is only known on the device: one spectrum per group keeps waves
+  // busy.  The listed spectra are few and the hardest (they fit for many
+  // iterations), so a wave's time is one long dependency chain: 16 lanes per
+  // spectrum halve each evaluation's chain against 8, at twice the solve work
+  // per spectrum.
+  if (n_cap <= 0) return hipSuccess;
+  return launch_lm_g<16>(y, p0, idx, count, n_cap, k, max_iter, 4, params, iters, status, chi2,
+                         status_code, nullptr, s);
 }
 
 }  // namespace cg
