@@ -132,6 +132,25 @@ __device__ __forceinline__ float key_float(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
+// #{q : keys[q] - base < piv} summed over a group of 16 lanes (unsigned
+// differences, so keys below base wrap to large values and do not count).
+// One compare and one add with carry per key, in two interleaved chains; the
+// empty asm keeps the compiler from packing the comparisons into a bit mask
+// and popcount.
+template <int Q>
+__device__ __forceinline__ int count_below16(const uint32_t (&keys)[Q], uint32_t piv,
+                                             uint32_t base = 0u) {
+  uint32_t ca = 0, cb = 0;
+#pragma unroll
+  for (int q = 0; q + 1 < Q; q += 2) {
+    ca += (uint32_t)(keys[q] - base < piv);
+    cb += (uint32_t)(keys[q + 1] - base < piv);
+    asm volatile("" : "+v"(ca), "+v"(cb));
+  }
+  if constexpr (Q % 2 == 1) ca += (uint32_t)(keys[Q - 1] - base < piv);
+  return sum16((int)(ca + cb));
+}
+
 // ---------------------------------------------------------------------------
 // Start point of the Lorentzian fit from one row of the 7x7-median image,
 // computed by a group of 16 lanes.  Lane gl of the group holds row values
@@ -185,8 +204,8 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
     // Gallop from a guess, the mean of the values at or above the row mean
     // (the dip pulls the plain mean below the baseline), in steps that double
     // until they leave [lo, hi]; this skips most of the probes that bisection
-    // from [min, max] spends outside the baseline cluster.
-    // (the repeated last tooth takes part: it moves the guess, not the result)
+    // from [min, max] spends outside the baseline cluster.  The repeated last
+    // tooth takes part in the guess: it moves the guess, not the result.
     float sm = 0.0f;
 #pragma unroll
     for (int q = 0; q < Q; ++q) sm += mv[q];
@@ -207,15 +226,7 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
     uint32_t step = (hi - lo) >> 8;
     step = step > 0u ? step : 1u;
     for (int p = 0; p < 10 && c_hi - c_lo > 4; ++p) {
-      uint32_t ca = 0, cb = 0;
-#pragma unroll
-      for (int q = 0; q + 1 < Q; q += 2) {
-        ca += (uint32_t)(keys[q] < mid);
-        cb += (uint32_t)(keys[q + 1] < mid);
-        asm volatile("" : "+v"(ca), "+v"(cb));
-      }
-      if constexpr (Q % 2 == 1) ca += (uint32_t)(keys[Q - 1] < mid);
-      const int c = sum16((int)(ca + cb));
+      const int c = count_below16(keys, mid);
       if (c <= r) {
         lo = mid;
         c_lo = c;
@@ -232,24 +243,13 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
   }
   while (lo < hi && c_hi - c_lo > 4) {
     const uint32_t mid = lo + ((hi - lo) >> 1) + 1u;  // lo < mid <= hi
-    // One compare and one add with carry per key, in two interleaved
-    // chains; the empty asm keeps the compiler from packing the comparisons
-    // into a bit mask and popcount.
-    uint32_t ca = 0, cb = 0;
-#pragma unroll
-    for (int q = 0; q + 1 < Q; q += 2) {
-      ca += (uint32_t)(keys[q] < mid);
-      cb += (uint32_t)(keys[q + 1] < mid);
-      asm volatile("" : "+v"(ca), "+v"(cb));
-    }
-    if constexpr (Q % 2 == 1) ca += (uint32_t)(keys[Q - 1] < mid);
-    uint32_t c = (uint32_t)sum16((int)(ca + cb));
-    if ((int)c <= r) {
+    const int c = count_below16(keys, mid);
+    if (c <= r) {
       lo = mid;
-      c_lo = (int)c;
+      c_lo = c;
     } else {
       hi = mid - 1u;
-      c_hi = (int)c;
+      c_hi = c;
     }
   }
   if (lo < hi) {
@@ -267,16 +267,8 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
         dmin = dq < dmin ? dq : dmin;
       }
       dmin = min16(dmin);
-      m = cur + dmin;
-      uint32_t ca = 0, cb = 0;
-#pragma unroll
-      for (int q = 0; q + 1 < Q; q += 2) {
-        ca += (uint32_t)(keys[q] - cur <= dmin);
-        cb += (uint32_t)(keys[q + 1] - cur <= dmin);
-        asm volatile("" : "+v"(ca), "+v"(cb));
-      }
-      if constexpr (Q % 2 == 1) ca += (uint32_t)(keys[Q - 1] - cur <= dmin);
-      c += sum16((int)(ca + cb));
+      m = cur + dmin;  // dmin + 1 does not wrap: a key <= hi < 2^32 - 1 is >= cur
+      c += count_below16(keys, dmin + 1u, cur);
       if (c > r) break;
       cur = m + 1u;
     }
@@ -294,16 +286,7 @@ __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float
   const float thr = __fmul_rn(med, __fsub_rn(1.0f, __fmul_rn(d, 0.5f)));
   // M < thr compared as keys (the same order for non-NaN values; the slots
   // past the end carry the largest key and never count)
-  const uint32_t tk = float_key(thr + 0.0f);
-  uint32_t ca = 0, cb = 0;
-#pragma unroll
-  for (int q = 0; q + 1 < Q; q += 2) {
-    ca += (uint32_t)(keys[q] < tk);
-    cb += (uint32_t)(keys[q + 1] < tk);
-    asm volatile("" : "+v"(ca), "+v"(cb));
-  }
-  if constexpr (Q % 2 == 1) ca += (uint32_t)(keys[Q - 1] < tk);
-  const int cnt = sum16((int)(ca + cb));
+  const int cnt = count_below16(keys, float_key(thr + 0.0f));
   c0 = (float)besti;
   w0 = (float)(cnt > 2 ? cnt : 2);
   d0 = d;
