@@ -194,6 +194,18 @@ cg_status cg_init_spectra(cg_plan* plan, const float* y, int64_t n_frames, float
                           float* out_median, void* stream);
 
 /*
+ * Start points for listed frames only (paper, Data Capture and Processing, as
+ * cg_init_spectra; the learned warm start re-runs this cold start for the
+ * frames whose network fit it rejects).  listed: device int32[n_frames];
+ * row f of out_p0 is written when listed[f] != 0 and left untouched
+ * otherwise.  The 7x7 median still reads the neighbouring frames of a listed
+ * one, listed or not, so its values are those cg_init_spectra gives.  Errors
+ * as for cg_init_spectra (CG_ERR_NULL for a NULL listed with n_frames > 0).
+ */
+cg_status cg_init_spectra_listed(cg_plan* plan, const float* y, int64_t n_frames,
+                                 const int32_t* listed, float* out_p0, void* stream);
+
+/*
  * The two kernels of cg_init_spectra, callable on their own:
  * cg_median_filter writes out_median = 7x7 median image of y (both device
  * float32 [n_frames][n_teeth], distinct buffers); cg_start_points turns a

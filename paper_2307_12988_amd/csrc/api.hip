@@ -368,6 +368,18 @@ cg_status cg_init_spectra(cg_plan* p, const float* y, int64_t nf, float* out_p0,
   return CG_OK;
 }
 
+cg_status cg_init_spectra_listed(cg_plan* p, const float* y, int64_t nf, const int32_t* listed,
+                                 float* out_p0, void* stream) {
+  if (!p || !out_p0) return CG_ERR_NULL;
+  if (nf < 0) return CG_ERR_INVALID_ARG;
+  if (nf == 0) return CG_OK;
+  if (!y || !listed) return CG_ERR_NULL;
+  hipError_t e =
+      cg::launch_median_start(y, nf, p->k, nullptr, out_p0, cg::pick(p, stream), listed);
+  if (e != hipSuccess) return hip_fail(e, "listed init launch");
+  return CG_OK;
+}
+
 cg_status cg_median_filter(cg_plan* p, const float* y, int64_t nf, float* out_median,
                            void* stream) {
   if (!p || !out_median) return CG_ERR_NULL;

@@ -207,6 +207,17 @@ class Plan:
         _lib.check(st, "cg_init_spectra")
         return p0, med
 
+    def init_spectra_listed(self, y, listed, out_p0):
+        """Start points for the frames with listed[f] != 0 (int32 device
+        tensor); the other rows of out_p0 are left as they are."""
+        nf = int(y.shape[0])
+        yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")
+        lp = _dev_ptr(listed, torch.int32, (nf,), "listed")
+        pp = _dev_ptr(out_p0, torch.float32, (nf, 4), "p0")
+        st = self._lib.cg_init_spectra_listed(self._h, yp, nf, lp, pp, _stream(y.device))
+        _lib.check(st, "cg_init_spectra_listed")
+        return out_p0
+
     def set_mlp(self, params, out_mean, out_std, noise_floor: float):
         """Install warm-start weights (flat float32 [MLP_NPARAMS])."""
         prm = np.ascontiguousarray(np.asarray(params), dtype=np.float32)

@@ -95,6 +95,7 @@ def test_null_arguments(lib):
     assert lib.cg_set_reference(None, None) == CODES["CG_ERR_NULL"]
     assert lib.cg_plan_info(None, None, None, None) == CODES["CG_ERR_NULL"]
     assert lib.cg_set_tuning(None, 1, 0) == CODES["CG_ERR_NULL"]
+    assert lib.cg_init_spectra_listed(None, None, 0, None, None, None) == CODES["CG_ERR_NULL"]
     assert lib.cg_median_filter(None, None, 0, None, None) == CODES["CG_ERR_NULL"]
     assert lib.cg_start_points(None, None, 0, None, None) == CODES["CG_ERR_NULL"]
     sz = ctypes.c_size_t()

@@ -154,6 +154,43 @@ def test_init_bit_exact_with_values_across_many_exponents(k):
     assert np.array_equal(p0.cpu().numpy(), oracle.initial_guess(y))
 
 
+@pytest.mark.parametrize("k,nf,pattern", [(220, 100, "none"), (220, 100, "all"),
+                                          (220, 100, "one"), (220, 100, "edges"),
+                                          (220, 1000, "random"), (220, 97, "alternate"),
+                                          (440, 61, "random"), (64, 33, "edges"), (7, 20, "one")])
+def test_init_listed_matches_oracle_on_listed_rows_only(k, nf, pattern):
+    """Start points for listed frames: listed rows bit-identical to the oracle,
+    the other rows untouched.  Patterns cover empty and full lists, a single
+    frame, frames at the edges of the 16-frame tiles and of the batch, every
+    other 4-frame step and a sparse random list."""
+    _say(f"init listed k={k} nf={nf} {pattern}")
+    rng = np.random.default_rng(nf + k)
+    c = rng.uniform(0, k - 1, nf)
+    i = np.arange(k)
+    y = 1.0 - 0.6 / (1 + (2 * (i[None, :] - c[:, None]) / 6.0) ** 2)
+    y = (y + 0.05 * rng.standard_normal(y.shape)).astype(np.float32)
+    listed = np.zeros(nf, dtype=np.int32)
+    if pattern == "all":
+        listed[:] = 1
+    elif pattern == "one":
+        listed[nf // 2] = 1
+    elif pattern == "edges":
+        listed[[f for f in (0, 15, 16, 31, nf - 1) if f < nf]] = 1
+    elif pattern == "random":
+        listed[rng.random(nf) < 0.14] = 7  # any non-zero value lists a frame
+    elif pattern == "alternate":
+        listed[(np.arange(nf) // 4) % 2 == 1] = 1
+    plan = cg.Plan(2048, 1e9, np.arange(1, k + 1), np.ones(k))
+    p0 = torch.full((nf, 4), -7.0, dtype=torch.float32, device=DEV)
+    plan.init_spectra_listed(torch.from_numpy(y).to(DEV), torch.from_numpy(listed).to(DEV), p0)
+    torch.cuda.synchronize()
+    got = p0.cpu().numpy()
+    want = oracle.initial_guess(y)
+    on = listed != 0
+    assert np.array_equal(got[on], want[on])
+    assert np.all(got[~on] == -7.0)
+
+
 def test_median_filter_and_start_points_separately():
     rng = np.random.default_rng(8)
     nf, k = 45, 220
