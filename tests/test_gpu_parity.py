@@ -157,7 +157,8 @@ def test_init_bit_exact_with_values_across_many_exponents(k):
 @pytest.mark.parametrize("k,nf,pattern", [(220, 100, "none"), (220, 100, "all"),
                                           (220, 100, "one"), (220, 100, "edges"),
                                           (220, 1000, "random"), (220, 97, "alternate"),
-                                          (440, 61, "random"), (64, 33, "edges"), (7, 20, "one")])
+                                          (440, 61, "random"), (64, 33, "edges"), (7, 20, "one"),
+                                          (220, 1, "all"), (1, 5, "all"), (300, 17, "one")])
 def test_init_listed_matches_oracle_on_listed_rows_only(k, nf, pattern):
     """Start points for listed frames: listed rows bit-identical to the oracle,
     the other rows untouched.  Patterns cover empty and full lists, a single
