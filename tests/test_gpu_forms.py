@@ -1,5 +1,5 @@
 """Precision form: tooth DFT on the matrix cores, per form, against the FP64
-oracle.  Bars (derived in the design doc from each form's rounding):
+oracle.  Bars, each derived from the form's rounding:
   BF16X3   samples split exactly, basis carried to ~2^-17: max rel amplitude
            error <= 1e-4 (the same bar as the FFT path);
   FP16X2   samples split exactly, basis rounded to fp16 (rel 2^-12 per entry):
