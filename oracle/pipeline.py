@@ -12,7 +12,9 @@ import numpy as np
 from .dft import tooth_magnitudes
 from .normalize import normalize
 from .initializer import initial_guess
-from .lm import lm_fit_batch
+from .lm import lm_fit, lm_fit_batch
+
+STATUS_FALLBACK = 3
 
 
 def process_batch(frames, bins, ref, max_iter: int = 20, tol: float = 1e-6):
@@ -26,26 +28,38 @@ def process_batch(frames, bins, ref, max_iter: int = 20, tol: float = 1e-6):
             "status": status, "chi2": chi2}
 
 
-def process_batch_warm(frames, bins, ref, params, out_mean, out_std, noise_floor,
-                       polish_iter: int = 2, max_iter: int = 20, tol: float = 1e-6):
-    """Learned warm start: network start point (bfloat16 operands emulated),
-    a short LM polish, and the cold-start fit for frames whose RMS residual
-    sqrt(chi2/(K-4)) exceeds 2 * noise_floor (status 3)."""
+def network_start(y, params, out_mean, out_std):
+    """Start points of the learned warm start for spectra y [F, K]: the
+    network's standardised outputs z mapped to p = z * std + mean, computed on
+    y resampled onto the network's 220 inputs; for K != 220 the centre and
+    width (tooth units) are scaled by (K - 1) / 219.  The spectra enter the
+    network as float32 values (bfloat16 operand rounding emulated)."""
     from . import mlp
-    from .lm import lm_fit
-    mags = tooth_magnitudes(frames, bins)
-    y = normalize(mags, ref)
+    y = np.asarray(y, dtype=np.float64)
     k = y.shape[1]
     x = mlp.resample_to_input(y.astype(np.float32).astype(np.float64))
     z, _ = mlp.forward(x, params, bf16_ops=True)
     p0 = z * np.asarray(out_std, dtype=np.float64) + np.asarray(out_mean, dtype=np.float64)
     p0[:, :2] *= (k - 1) / (mlp.IN - 1)
+    return p0
+
+
+def warm_fit(y, p0, noise_floor, polish_iter: int = 2, max_iter: int = 20, tol: float = 1e-6):
+    """Polish each spectrum from its warm start point p0 by `polish_iter` LM
+    iterations; a frame whose RMS residual sqrt(chi2 / (K - 4)) then exceeds
+    2 * noise_floor (or is not finite) is fitted again from the cold start
+    point (7x7 median) with up to `max_iter` iterations and gets status 3.
+    Its reported iteration count is the refit's.  Returns (params, iters,
+    status, chi2, fell_back)."""
+    y = np.asarray(y, dtype=np.float64)
+    f_count, k = y.shape
     cold_p0 = None
-    f_count = y.shape[0]
     params_out = np.empty((f_count, 4))
     iters = np.empty(f_count, dtype=np.int32)
     status = np.empty(f_count, dtype=np.int32)
     chi2 = np.empty(f_count)
+    fell = np.zeros(f_count, dtype=bool)
+    # RMS residual > 2 sigma  <=>  chi2 > 4 sigma^2 (K - 4)
     thr2 = 4.0 * noise_floor ** 2 * max(k - 4, 1)
     for f in range(f_count):
         p, it, st, c2 = lm_fit(y[f], p0[f], polish_iter, tol)
@@ -53,7 +67,20 @@ def process_batch_warm(frames, bins, ref, params, out_mean, out_std, noise_floor
             if cold_p0 is None:
                 cold_p0 = initial_guess(y)
             p, it, st, c2 = lm_fit(y[f], cold_p0[f], max_iter, tol)
-            st = 3
+            st = STATUS_FALLBACK
+            fell[f] = True
         params_out[f], iters[f], status[f], chi2[f] = p, it, st, c2
+    return params_out, iters, status, chi2, fell
+
+
+def process_batch_warm(frames, bins, ref, params, out_mean, out_std, noise_floor,
+                       polish_iter: int = 2, max_iter: int = 20, tol: float = 1e-6):
+    """Learned warm start for a batch of frames: transform, teeth, reference
+    division, network start point, short LM polish, cold-start refit of the
+    frames the residual test rejects (status 3)."""
+    mags = tooth_magnitudes(frames, bins)
+    y = normalize(mags, ref)
+    p0 = network_start(y, params, out_mean, out_std)
+    params_out, iters, status, chi2, _ = warm_fit(y, p0, noise_floor, polish_iter, max_iter, tol)
     return {"mags": mags, "y": y, "p0": p0, "params": params_out, "iters": iters,
             "status": status, "chi2": chi2}

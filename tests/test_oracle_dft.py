@@ -140,3 +140,30 @@ def test_paper_geometry_fixture():
     assert np.array_equal(synth.tooth_bins_paper_c1(), (beat / bin_hz).astype(np.int32))
     span = 100 * g["comb_spacing_hz"]["value"]
     assert span <= g["comb_span_hz"]["value"]
+
+
+def test_reference_is_mean_of_amplitudes_over_frames():
+    """Three reference frames whose teeth have exact integer samples (DC,
+    N/4 and Nyquist) with different amplitudes and phases: the reference is
+    the arithmetic mean of the per-frame amplitudes, which differs from their
+    sum, their median, their RMS and the amplitude of the complex mean."""
+    n = 1024
+    t = np.arange(n)
+    quarter_cos = np.array([1, 0, -1, 0])[t % 4]
+    quarter_sin = np.array([0, 1, 0, -1])[t % 4]        # the same tone, 90 degrees on
+    nyq = np.where(t % 2 == 0, 1, -1)
+    amps = [(3, 100, 5), (-7, 200, 11), (20, 900, -2)]   # (DC, N/4 tone, Nyquist)
+    frames = []
+    for j, (a0, a1, a2) in enumerate(amps):
+        tone = quarter_cos if j != 1 else quarter_sin
+        frames.append(a0 + a1 * tone + a2 * nyq)
+    frames = np.array(frames, dtype=np.int16)
+    bins = [0, n // 4, n // 2]
+    ref = oracle.reference_spectrum(frames, bins)
+    per_frame = np.array([[abs(a0) * n, abs(a1) * n / 2, abs(a2) * n] for a0, a1, a2 in amps])
+    want = per_frame.mean(axis=0)
+    assert np.allclose(ref, want, rtol=1e-12)
+    assert not np.allclose(want, np.median(per_frame, axis=0))
+    assert not np.allclose(want, np.sqrt((per_frame ** 2).mean(axis=0)))
+    coherent = np.abs(np.fft.rfft(frames.astype(np.float64), axis=1).mean(axis=0)[bins])
+    assert abs(want[1] - coherent[1]) > 1.0
