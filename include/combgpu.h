@@ -295,12 +295,23 @@ cg_status cg_mlp_get_params(cg_mlp_trainer* trainer, float* params);
 
 /*
  * Tuning knobs of a plan (launch shapes only; results do not depend on them).
- *   CG_TUNE_LM_CHUNK  spectra per wavefront in the fit kernel: 0 = chosen from
- *                     the batch size (default), else a multiple of 4 in 4..256.
+ *   CG_TUNE_LM_CHUNK    spectra per wavefront in the fit kernel: 0 = chosen
+ *                       from the batch size (default), else a multiple of 4 in
+ *                       4..256.
+ *   CG_TUNE_LM_LANES    lanes per spectrum in the fit kernel: 0 = 8 up to 224
+ *                       teeth, else 16 (default); 8 (only up to 224 teeth) or
+ *                       16.
+ *   CG_TUNE_FFT_BLOCKS  cap on the persistent FFT kernel's grid: 0 = every
+ *                       block that fits on the device at once (default), else
+ *                       at most that many blocks.
+ * cg_get_tuning reads a knob back.
  * Errors: CG_ERR_INVALID_ARG for an unknown knob or value out of range.
  */
-#define CG_TUNE_LM_CHUNK 1
+#define CG_TUNE_LM_CHUNK   1
+#define CG_TUNE_LM_LANES   2
+#define CG_TUNE_FFT_BLOCKS 3
 cg_status cg_set_tuning(cg_plan* plan, int32_t knob, int32_t value);
+cg_status cg_get_tuning(const cg_plan* plan, int32_t knob, int32_t* value);
 
 /*
  * Multi-stream ring pipeline (paper: ring buffer between digitiser and GPU,
@@ -313,9 +324,13 @@ cg_status cg_set_tuning(cg_plan* plan, int32_t knob, int32_t value);
  * CG_FIT_WARM_MLP) and slots_per_stream device slots of max_burst_frames
  * frames.  Each slot's processing chain is captured once as a hipGraph; a
  * persistent dispatcher thread launches published bursts in publish order on
- * one HIP stream per stream (default priority) and records the host-clock
- * latency from publish to results in pinned host memory.  Plans must outlive
- * the pipeline and must not change while it exists.
+ * one HIP stream per stream (default priority); it is the only thread that
+ * enqueues on those streams (the copies cg_pipeline_put asks for included).
+ * Latency from publish to results is recorded on the host clock (until the
+ * dispatcher sees the burst complete) and on the GPU's wall clock (until the
+ * results are in host memory; the publish time is mapped onto the GPU clock
+ * by the smallest launch-to-start gap seen in the last second or two).  Plans
+ * must outlive the pipeline and must not change while it exists.
  *
  * options: CG_PIPE_KEEP_RESULTS keeps each completed burst's results (and its
  * slot) until cg_pipeline_read; without it slots are recycled on completion.
@@ -343,29 +358,41 @@ cg_status cg_pipeline_publish(cg_pipeline* pipe, int32_t stream, int32_t slot, i
                               int64_t seq);
 /* Acquire + copy + publish in one call: src holds n_frames frames of the
  * stream's frame length in host or device memory (any address HIP can copy
- * from; the copy is queued on the stream's HIP stream ahead of the burst, so
- * a host source must stay unchanged until the burst completes and is best
- * pinned).  CG_ERR_RING_FULL as for cg_pipeline_acquire. */
+ * from).  The dispatcher queues the copy on the stream's HIP stream just
+ * before the burst's graph, so src must stay valid and unchanged until the
+ * burst completes; a host source is best pinned (a pageable one makes the
+ * dispatcher wait for the copy).  CG_ERR_RING_FULL as for
+ * cg_pipeline_acquire. */
 cg_status cg_pipeline_put(cg_pipeline* pipe, int32_t stream, const int16_t* src, int32_t n_frames,
                           int64_t seq);
-/* Pop the oldest completed burst of `stream` (CG_PIPE_KEEP_RESULTS): params
- * host float32 [n][4], status host int32 [n] (either may be NULL), capacity in
- * frames; CG_ERR_STATE when none is ready or the order was violated. */
+/* Pop the next burst of `stream` in publish order (CG_PIPE_KEEP_RESULTS),
+ * once it has completed: bursts that complete before an earlier burst of
+ * their stream are held until it has (the paper's re-sort of out-of-order
+ * batches).  params host float32 [n][4], status host int32 [n] (either may be
+ * NULL), capacity in frames.  CG_ERR_STATE with *n_frames = 0 when the next
+ * burst is not ready (or none is queued); CG_ERR_STATE with the burst
+ * dropped when its seq is not above the previous one read. */
 cg_status cg_pipeline_read(cg_pipeline* pipe, int32_t stream, float* params, int32_t* status,
                            int32_t capacity, int32_t* n_frames, int64_t* seq);
 /* Wait until every published burst has completed (CG_ERR_STATE on timeout). */
 cg_status cg_pipeline_drain(cg_pipeline* pipe, int32_t timeout_ms);
 /* Counters since creation, out[CG_PIPE_NSTATS]: bursts, frames, bytes of
  * int16 input, overflows, seconds from first publish to last completion,
- * latency p50, p99, max (ms), bytes/s, frames/s. */
-#define CG_PIPE_NSTATS 10
+ * host-clock latency p50, p99, max (ms), bytes/s, frames/s, GPU-clock
+ * latency publish -> results p50, p99, max (ms), GPU-clock span graph start
+ * -> results p50 (ms).  In dry-run mode the GPU-clock figures are the host
+ * clock's. */
+#define CG_PIPE_NSTATS 14
 cg_status cg_pipeline_stats(cg_pipeline* pipe, double* out, int32_t n_out);
 
 /*
  * Autotuner: times the whole path (flags as for cg_process_batch_ex) on the
- * given frames for each fit-kernel launch shape (spectra per wavefront 4, 8,
- * 16, 32, 64), installs the fastest in the plan and returns it (*chosen) and
- * its time per batch (*best_ms, may be NULL).  Synchronises the device.
+ * given frames for each launch shape -- fit-kernel lanes per spectrum (8 when
+ * the teeth allow it, 16) x spectra per wavefront (1, 2, 4, 8 per lane group)
+ * x FFT grid (every resident block, half of them) -- installs the fastest in
+ * the plan (read it back with cg_get_tuning) and returns its spectra per
+ * wavefront (*chosen) and its time per batch (*best_ms, may be NULL).
+ * Synchronises the device; allocates a parameter buffer for the timing.
  */
 cg_status cg_autotune(cg_plan* plan, const int16_t* frames, int64_t n_frames, uint32_t flags,
                       void* workspace, size_t workspace_bytes, int32_t* chosen, float* best_ms);

@@ -42,6 +42,7 @@ SIGNATURES = {
     "cg_start_points": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_fit_spectra": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp]),
     "cg_set_tuning": (_i32, [_vp, _i32, _i32]),
+    "cg_get_tuning": (_i32, [_vp, _i32, _pi32]),
     "cg_set_mlp": (_i32, [_vp, _pf32, _pf32, _pf32, _c.c_float]),
     "cg_set_polish_iters": (_i32, [_vp, _i32]),
     "cg_mlp_infer": (_i32, [_vp, _vp, _i64, _vp, _vp]),

@@ -305,7 +305,7 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
     e = cg::launch_mlp_infer(p->mlp, y, nf, p->k, p0, s);
     if (e == hipSuccess)
       e = cg::launch_lm(y, p0, nf, p->k, p->polish_iters, out_params, out_iters, out_status,
-                        chi2, s, p->lm_chunk, nullptr, fb_count);
+                        chi2, s, p->lm_chunk, nullptr, fb_count, p->lm_lanes);
     if (e == hipSuccess)
       e = cg::launch_fallback_select(chi2, nf, p->k, p->mlp->noise_floor, fb_flags, fb_idx,
                                      fb_count, s);
@@ -319,7 +319,7 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
   e = cg::launch_median_start(y, nf, p->k, nullptr, p0, s);
   if (e != hipSuccess) return hip_fail(e, "median/start launch");
   e = cg::launch_lm(y, p0, nf, p->k, 20, out_params, out_iters, out_status, out_chi2, s,
-                    p->lm_chunk);
+                    p->lm_chunk, nullptr, nullptr, p->lm_lanes);
   if (e != hipSuccess) return hip_fail(e, "lm launch");
   return CG_OK;
 }
@@ -412,7 +412,7 @@ cg_status cg_fit_spectra(cg_plan* p, const float* y, const float* p0, int64_t nf
   if (!y || !p0) return CG_ERR_NULL;
   const hipStream_t s = cg::pick(p, stream);
   hipError_t e = cg::launch_lm(y, p0, nf, p->k, max_iter, out_params, out_iters, out_status,
-                               out_chi2, s, p->lm_chunk);
+                               out_chi2, s, p->lm_chunk, nullptr, nullptr, p->lm_lanes);
   if (e != hipSuccess) return hip_fail(e, "lm launch");
   return CG_OK;
 }
@@ -505,12 +505,31 @@ cg_status cg_set_polish_iters(cg_plan* p, int32_t iters) {
   return CG_OK;
 }
 
+cg_status cg_get_tuning(const cg_plan* p, int32_t knob, int32_t* value) {
+  if (!p || !value) return CG_ERR_NULL;
+  switch (knob) {
+    case CG_TUNE_LM_CHUNK: *value = p->lm_chunk; return CG_OK;
+    case CG_TUNE_LM_LANES: *value = p->lm_lanes; return CG_OK;
+    case CG_TUNE_FFT_BLOCKS: *value = p->fft_cap; return CG_OK;
+    default: return CG_ERR_INVALID_ARG;
+  }
+}
+
 cg_status cg_set_tuning(cg_plan* p, int32_t knob, int32_t value) {
   if (!p) return CG_ERR_NULL;
   switch (knob) {
     case CG_TUNE_LM_CHUNK:
       if (value != 0 && (value < 4 || value > 256 || value % 4 != 0)) return CG_ERR_INVALID_ARG;
       p->lm_chunk = value;
+      return CG_OK;
+    case CG_TUNE_LM_LANES:
+      if (value != 0 && value != 8 && value != 16) return CG_ERR_INVALID_ARG;
+      if (value == 8 && p->k > 224) return CG_ERR_INVALID_ARG;
+      p->lm_lanes = value;
+      return CG_OK;
+    case CG_TUNE_FFT_BLOCKS:
+      if (value < 0) return CG_ERR_INVALID_ARG;
+      p->fft_cap = value;
       return CG_OK;
     default:
       return CG_ERR_INVALID_ARG;

@@ -483,6 +483,7 @@ hipError_t launch_tt(const cg_plan* p, const int16_t* frames, int64_t nf, float*
   using S = FftShape<LOGM>;
   int64_t blocks = (nf + S::FPB - 1) / S::FPB;
   if (p->fft_blocks > 0 && blocks > p->fft_blocks) blocks = p->fft_blocks;
+  if (p->fft_cap > 0 && blocks > p->fft_cap) blocks = p->fft_cap;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   if (blocks == 0) return hipSuccess;
   fft_teeth_kernel<LOGM, TPT><<<dim3((unsigned)blocks), dim3(256), fft_lds_bytes<LOGM>(p->k),

@@ -29,6 +29,8 @@ struct cg_plan {
   size_t ws_bytes = 0;
   cg_mlp* mlp = nullptr;
   int32_t lm_chunk = 0;        // spectra per wave in the fit kernel (0 = auto)
+  int32_t lm_lanes = 0;        // lanes per spectrum in the fit kernel (0 = auto, 8, 16)
+  int32_t fft_cap = 0;         // tuned cap on the FFT grid (0 = every resident block)
   int32_t polish_iters = 2;    // LM iterations from the network's start point
   int32_t fft_blocks = 0;      // resident blocks of the FFT kernel on the device (0 = no cap)
   // tooth-DFT bases for the matrix-core forms, [ceil(k/64)*64][n], built on
@@ -81,14 +83,15 @@ hipError_t launch_start_points(const float* m, int64_t n_frames, int k, float* o
 
 // A5: Levenberg-Marquardt from start points p0.  chunk = spectra per wave
 // (<= 0: chosen from n_frames and the tooth count).
+// lanes = lanes per spectrum (8 or 16; 0: 8 up to 224 teeth, else 16).
 int lm_group(int n_teeth);
-int lm_chunk(int64_t n_frames, int n_teeth);
+int lm_chunk(int64_t n_frames, int n_teeth, int lanes = 0);
 // zero_count, if not null, is set to 0 by the kernel (for a counter the next
 // kernel on the stream accumulates into).
 hipError_t launch_lm(const float* y, const float* p0, int64_t n_frames, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
                      int chunk = 0, const int32_t* dev_n = nullptr,
-                     int32_t* zero_count = nullptr);
+                     int32_t* zero_count = nullptr, int lanes = 0);
 // Indexed form: fit frames idx[0..*count) (count read on the device, at most
 // n_cap); every reported status is replaced by status_code.
 hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx,

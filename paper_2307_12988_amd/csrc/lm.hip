@@ -422,11 +422,11 @@ hipError_t launch_fallback_select(const float* chi2, int64_t nf, int k, float no
 // the solve and the decisions over more spectra and shorten the reductions.
 int lm_group(int k) { return k <= 224 ? 8 : 16; }
 
-int lm_chunk(int64_t nf, int k) {
+int lm_chunk(int64_t nf, int k, int lanes) {
   // spectra per wave: about four per group, so a group that finishes early
   // has work to take, while keeping at least 2048 waves (two per SIMD) when
   // the batch allows it
-  const int ng = 64 / lm_group(k);
+  const int ng = 64 / (lanes > 0 ? lanes : lm_group(k));
   int64_t c = nf / 2048;
   if (c > 4 * ng) c = 4 * ng;
   c = (c / ng) * ng;
@@ -477,9 +477,12 @@ hipError_t launch_lm_g(const float* y, const float* p0, const int32_t* idx,
 hipError_t launch_lm_any(const float* y, const float* p0, const int32_t* idx,
                          const int32_t* count, int64_t nf, int k, int max_iter, int chunk,
                          float* params, int32_t* iters, int32_t* status, float* chi2,
-                         int32_t status_code, int32_t* zero_count, hipStream_t s) {
+                         int32_t status_code, int32_t* zero_count, hipStream_t s, int lanes) {
   if (nf <= 0) return hipSuccess;
-  if (lm_group(k) == 8)
+  if (lanes != 0 && lanes != 8 && lanes != 16) return hipErrorInvalidValue;
+  if (lanes == 0) lanes = lm_group(k);
+  if (lanes == 8 && k > 8 * 28) return hipErrorInvalidValue;
+  if (lanes == 8)
     return launch_lm_g<8>(y, p0, idx, count, nf, k, max_iter, chunk, params, iters, status,
                           chi2, status_code, zero_count, s);
   return launch_lm_g<16>(y, p0, idx, count, nf, k, max_iter, chunk, params, iters, status,
@@ -490,10 +493,10 @@ hipError_t launch_lm_any(const float* y, const float* p0, const int32_t* idx,
 
 hipError_t launch_lm(const float* y, const float* p0, int64_t nf, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
-                     int chunk, const int32_t* dev_n, int32_t* zero_count) {
-  if (chunk <= 0) chunk = lm_chunk(nf, k);
+                     int chunk, const int32_t* dev_n, int32_t* zero_count, int lanes) {
+  if (chunk <= 0) chunk = lm_chunk(nf, k, lanes);
   return launch_lm_any(y, p0, nullptr, dev_n, nf, k, max_iter, chunk, params, iters, status,
-                       chi2, -1, zero_count, s);
+                       chi2, -1, zero_count, s, lanes);
 }
 
 hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx,
@@ -506,8 +509,8 @@ hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx
   // spectrum halve each evaluation's chain against 8, at twice the solve work
   // per spectrum.
   if (n_cap <= 0) return hipSuccess;
-  return launch_lm_g<16>(y, p0, idx, count, n_cap, k, max_iter, 4, params, iters, status, chi2,
-                         status_code, nullptr, s);
+  return launch_lm_any(y, p0, idx, count, n_cap, k, max_iter, 4, params, iters, status, chi2,
+                       status_code, nullptr, s, 16);
 }
 
 }  // namespace cg

@@ -19,14 +19,25 @@
 //   point, fit, fallback) is captured once into a hipGraph with the slot's
 //   fixed buffers; the burst size is read by the kernels from a device count
 //   in the slot, so one graph serves any burst up to `cap`.
-// * Dispatcher: one persistent host thread drains the queue in publish order:
-//   per burst it writes the count to the slot's pinned word, launches the
-//   slot's graph on the stream's HIP stream (the graph reads the count and
-//   writes the results to pinned host memory itself) and records an event; it
-//   polls the events and records publish-to-results latency on the host
-//   clock.  Work of different streams overlaps on the GPU; within a
-//   stream bursts complete in order, so per-stream results come out in seq
-//   order (checked on read).
+// * Dispatcher: one persistent host thread drains the queue in publish order
+//   and is the only thread that enqueues work on the streams' HIP streams:
+//   per burst it issues the copy a cg_pipeline_put asked for, writes the
+//   count to the slot's pinned word, launches the slot's graph (the graph
+//   reads the count and writes the results to pinned host memory itself) and
+//   records an event.  It polls the events without holding the pipeline's
+//   lock (producers only wait for it to move slots between states).  Work of
+//   different streams overlaps on the GPU; within a stream bursts complete in
+//   order; whatever the completion order, cg_pipeline_read hands a stream's
+//   results out in publish order (a burst that completes early waits for
+//   the earlier ones of its stream, as the paper re-sorts batches).
+// * Latency: the graph stamps the GPU's constant-rate wall clock when it
+//   starts and after the results are written.  The host clock and the GPU
+//   clock are tied by the smallest (graph start - launch call) seen in the
+//   last second or two (a launch cannot start before it is issued, and the
+//   quickest launches start within microseconds), which maps the publish
+//   time onto the GPU clock: publish -> results written is then read off
+//   the GPU's own clock.  The host-clock publish -> completion-seen latency
+//   is kept beside it.
 // * Dry run (CG_PIPE_DRY_RUN): the same bookkeeping with no device work; a
 //   burst "completes" after dry_us_per_frame * n microseconds.  Used to test
 //   overflow handling and ordering on machines without a GPU.
@@ -54,6 +65,10 @@ double now_s() {
 
 enum SlotState : int { FREE = 0, WRITING = 1, QUEUED = 2, RUNNING = 3, DONE = 4 };
 
+struct Burst {
+  int stream, slot;
+};
+
 struct PipeSlot {
   int16_t* frames = nullptr;
   int32_t* n_dev = nullptr;
@@ -73,13 +88,17 @@ struct PipeSlot {
   int32_t* h_status = nullptr;  // pinned
   float* h_params_dev = nullptr;   // device views of the pinned results
   int32_t* h_status_dev = nullptr;
+  unsigned long long* h_ts = nullptr;      // pinned: GPU clock at graph start, results written
+  unsigned long long* h_ts_dev = nullptr;  // device view of h_ts
+  const void* src = nullptr;  // copy source handed in by cg_pipeline_put (or null)
+  size_t src_bytes = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;
   int state = FREE;
   int64_t seq = 0;
   int32_t n = 0;
-  double t_pub = 0.0, t_done = 0.0;
+  double t_pub = 0.0, t_launch = 0.0, t_done = 0.0;
 };
 
 struct PipeStream {
@@ -89,7 +108,7 @@ struct PipeStream {
   std::vector<PipeSlot> slots;
   int cursor = 0;
   int64_t last_seq_read = -1;
-  std::deque<int> completed;  // slot indices in completion (= publish) order
+  std::deque<int> published;  // slot indices in publish order (read order)
   int64_t bursts = 0, frames = 0;
 };
 
@@ -104,8 +123,8 @@ struct cg_pipeline {
   std::vector<PipeStream> st;
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<std::pair<int, int>> queue;
-  std::vector<std::pair<int, int>> running;
+  std::deque<Burst> queue;
+  int64_t in_flight = 0;  // taken off the queue by the dispatcher, not yet completed
   std::thread worker;
   bool stop = false;
   bool failed = false;
@@ -113,7 +132,13 @@ struct cg_pipeline {
   int64_t overflows = 0, bursts = 0, frames = 0;
   double bytes = 0.0;
   double t_first = -1.0, t_last = 0.0;
-  std::vector<float> lat_ms;
+  std::vector<float> lat_ms;      // host clock: publish -> completion seen
+  std::vector<float> dev_lat_ms;  // GPU clock: publish (mapped) -> results written
+  std::vector<float> dev_span_ms; // GPU clock: graph start -> results written
+  double clk_hz = 1e8;            // GPU wall-clock rate
+  // host time = GPU clock / clk_hz - offset; offset estimated by the
+  // smallest launch-to-start gap, over the current and the previous second
+  double off_cur = 1e300, off_prev = 1e300, off_epoch = 0.0;
 };
 
 namespace cg {
@@ -127,8 +152,16 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 // reads it over the bus into the slot's device count) and the results leave
 // it the same way, written straight into pinned host buffers: a burst costs
 // the dispatcher one graph launch and one event record.
-__global__ void count_in_kernel(const int32_t* __restrict__ host_n, int32_t* __restrict__ n) {
+__global__ void count_in_kernel(const int32_t* __restrict__ host_n, int32_t* __restrict__ n,
+                                unsigned long long* __restrict__ ts) {
+  ts[0] = (unsigned long long)wall_clock64();
   n[0] = host_n[0];
+}
+
+// Runs after the results kernel on the same stream: the GPU clock once the
+// burst's results are in host memory.
+__global__ void stamp_done_kernel(unsigned long long* __restrict__ ts) {
+  ts[1] = (unsigned long long)wall_clock64();
 }
 
 __global__ __launch_bounds__(256) void results_out_kernel(const int32_t* __restrict__ n_dev,
@@ -149,14 +182,15 @@ hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
   hipStream_t s = ps.hs;
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(count_in_kernel, dim3(1), dim3(1), 0, s, sl.n_host_dev, sl.n_dev);
+  hipLaunchKernelGGL(count_in_kernel, dim3(1), dim3(1), 0, s, sl.n_host_dev, sl.n_dev,
+                     sl.h_ts_dev);
   hipError_t le = hipGetLastError();
   if (le == hipSuccess) le = launch_fft_teeth(p, sl.frames, cap, nullptr, sl.y, s, sl.n_dev);
   if ((ps.flags & CG_FIT_MASK) == CG_FIT_WARM_MLP) {
     if (le == hipSuccess) le = launch_mlp_infer(p->mlp, sl.y, cap, p->k, sl.p0, s, sl.n_dev);
     if (le == hipSuccess)
       le = launch_lm(sl.y, sl.p0, cap, p->k, p->polish_iters, sl.params, sl.iters, sl.status,
-                     sl.chi2, s, p->lm_chunk, sl.n_dev, sl.fb_count);
+                     sl.chi2, s, p->lm_chunk, sl.n_dev, sl.fb_count, p->lm_lanes);
     if (le == hipSuccess)
       le = launch_fallback_select(sl.chi2, cap, p->k, p->mlp->noise_floor, sl.fb_flags, sl.fb_idx,
                                   sl.fb_count, s, sl.n_dev);
@@ -170,13 +204,17 @@ hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
       le = launch_median_start(sl.y, cap, p->k, nullptr, sl.p0, s, nullptr, sl.n_dev);
     if (le == hipSuccess)
       le = launch_lm(sl.y, sl.p0, cap, p->k, 20, sl.params, sl.iters, sl.status, sl.chi2, s,
-                     p->lm_chunk, sl.n_dev);
+                     p->lm_chunk, sl.n_dev, nullptr, p->lm_lanes);
   }
   if (le == hipSuccess) {
     const int blocks = (cap + 255) / 256 < 64 ? (cap + 255) / 256 : 64;
     hipLaunchKernelGGL(results_out_kernel, dim3(blocks), dim3(256), 0, s, sl.n_dev, cap,
                        reinterpret_cast<const float4*>(sl.params), sl.status,
                        reinterpret_cast<float4*>(sl.h_params_dev), sl.h_status_dev);
+    le = hipGetLastError();
+  }
+  if (le == hipSuccess) {
+    hipLaunchKernelGGL(stamp_done_kernel, dim3(1), dim3(1), 0, s, sl.h_ts_dev);
     le = hipGetLastError();
   }
   e = hipStreamEndCapture(s, &sl.graph);
@@ -194,6 +232,7 @@ void free_slot(PipeSlot& sl) {
   if (sl.n_host) (void)hipHostFree(sl.n_host);
   if (sl.h_params) (void)hipHostFree(sl.h_params);
   if (sl.h_status) (void)hipHostFree(sl.h_status);
+  if (sl.h_ts) (void)hipHostFree(sl.h_ts);
 }
 
 hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
@@ -226,6 +265,8 @@ hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
   if ((e = hipHostMalloc(&sl.n_host, sizeof(int32_t))) != hipSuccess) return e;
   if ((e = hipHostMalloc(&sl.h_params, (size_t)cap * 16)) != hipSuccess) return e;
   if ((e = hipHostMalloc(&sl.h_status, (size_t)cap * 4)) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&sl.h_ts, 2 * sizeof(unsigned long long))) != hipSuccess) return e;
+  sl.h_ts[0] = sl.h_ts[1] = 0;
   if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.n_host_dev), sl.n_host, 0)) !=
       hipSuccess)
     return e;
@@ -235,23 +276,37 @@ hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
   if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.h_status_dev), sl.h_status, 0)) !=
       hipSuccess)
     return e;
+  if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.h_ts_dev), sl.h_ts, 0)) !=
+      hipSuccess)
+    return e;
   if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) return e;
   return capture_slot(ps, sl, cap);
 }
 
-// launch one burst (dispatcher thread, no lock held)
-hipError_t launch_burst(cg_pipeline* P, int si, int li) {
-  PipeStream& ps = P->st[si];
-  PipeSlot& sl = ps.slots[li];
+// launch one burst (dispatcher thread, no lock held): the queued copy if any,
+// then the slot's graph and its completion event, all on the stream's own HIP
+// stream, which no other thread enqueues on
+hipError_t launch_burst(cg_pipeline* P, const Burst& q) {
+  PipeStream& ps = P->st[q.stream];
+  PipeSlot& sl = ps.slots[q.slot];
+  hipError_t e = hipSuccess;
+  if (sl.src) e = hipMemcpyAsync(sl.frames, sl.src, sl.src_bytes, hipMemcpyDefault, ps.hs);
   *sl.n_host = sl.n;  // read by the graph's first kernel
-  hipError_t e = hipGraphLaunch(sl.exec, ps.hs);
+  sl.t_launch = now_s();
+  if (e == hipSuccess) e = hipGraphLaunch(sl.exec, ps.hs);
   if (e == hipSuccess) e = hipEventRecord(sl.done, ps.hs);
   return e;
 }
 
-void complete(cg_pipeline* P, int si, int li, double t) {
-  PipeStream& ps = P->st[si];
-  PipeSlot& sl = ps.slots[li];
+template <typename T>
+void keep_sample(std::vector<T>& v, double x) {
+  if (v.size() < kLatKeep) v.push_back((T)x);
+}
+
+// bookkeeping of a completed burst (lock held)
+void complete(cg_pipeline* P, const Burst& q, double t) {
+  PipeStream& ps = P->st[q.stream];
+  PipeSlot& sl = ps.slots[q.slot];
   sl.t_done = t;
   ps.bursts += 1;
   ps.frames += sl.n;
@@ -259,71 +314,92 @@ void complete(cg_pipeline* P, int si, int li, double t) {
   P->frames += sl.n;
   P->bytes += (double)sl.n * (P->dry ? 0.0 : (double)ps.plan->n * 2.0);
   P->t_last = t;
-  if (P->lat_ms.size() < kLatKeep) P->lat_ms.push_back((float)((t - sl.t_pub) * 1e3));
-  if (P->keep) {
-    sl.state = DONE;
-    ps.completed.push_back(li);
+  keep_sample(P->lat_ms, (t - sl.t_pub) * 1e3);
+  if (P->dry) {
+    keep_sample(P->dev_lat_ms, (t - sl.t_pub) * 1e3);
+    keep_sample(P->dev_span_ms, (t - sl.t_launch) * 1e3);
   } else {
-    sl.state = FREE;
+    const double g0 = (double)sl.h_ts[0] / P->clk_hz, g1 = (double)sl.h_ts[1] / P->clk_hz;
+    // GPU clock minus host clock, bounded below by the launch-to-start gap
+    const double gap = g0 - sl.t_launch;
+    if (t - P->off_epoch > 1.0) {
+      P->off_prev = P->off_cur;
+      P->off_cur = 1e300;
+      P->off_epoch = t;
+    }
+    P->off_cur = std::min(P->off_cur, gap);
+    const double off = std::min(P->off_cur, P->off_prev);
+    keep_sample(P->dev_lat_ms, (g1 - off - sl.t_pub) * 1e3);
+    keep_sample(P->dev_span_ms, (g1 - g0) * 1e3);
   }
+  sl.src = nullptr;
+  sl.src_bytes = 0;
+  sl.state = P->keep ? DONE : FREE;
 }
 
 void dispatcher(cg_pipeline* P) {
   if (!P->dry) (void)hipSetDevice(P->device);
-  std::vector<std::pair<int, int>> todo;
+  std::vector<Burst> todo, inflight, finished, still;
+  std::vector<hipError_t> errs;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(P->mu);
-      if (P->queue.empty() && P->running.empty()) {
+      if (P->queue.empty() && inflight.empty()) {
         P->cv.notify_all();  // idle: wake drain()
         P->cv.wait_for(lk, std::chrono::microseconds(200),
                        [&] { return P->stop || !P->queue.empty(); });
-        if (P->stop && P->queue.empty() && P->running.empty()) return;
+        if (P->stop && P->queue.empty() && inflight.empty()) return;
       }
       todo.assign(P->queue.begin(), P->queue.end());
       P->queue.clear();
-      for (auto& q : todo) P->st[q.first].slots[q.second].state = RUNNING;
+      P->in_flight += (int64_t)todo.size();
+      for (auto& q : todo) P->st[q.stream].slots[q.slot].state = RUNNING;
     }
-    // launches, in publish order
+    // launches, in publish order (slot contents are only read here and by
+    // the dispatcher's completion step while the slot is RUNNING)
     for (auto& q : todo) {
-      if (!P->dry) {
-        hipError_t e = launch_burst(P, q.first, q.second);
+      if (P->dry) {
+        P->st[q.stream].slots[q.slot].t_launch = now_s();
+      } else {
+        const hipError_t e = launch_burst(P, q);
         if (e != hipSuccess) {
           std::lock_guard<std::mutex> lk(P->mu);
           P->failed = true;
           P->fail_detail = std::string("pipeline launch: ") + hipGetErrorString(e);
         }
       }
-      std::lock_guard<std::mutex> lk(P->mu);
-      P->running.push_back(q);
+      inflight.push_back(q);
     }
     todo.clear();
-    // completions
-    {
-      std::lock_guard<std::mutex> lk(P->mu);
-      const double t = now_s();
-      std::vector<std::pair<int, int>> still;
-      for (auto& q : P->running) {
-        PipeSlot& sl = P->st[q.first].slots[q.second];
-        bool finished;
-        if (P->dry) {
-          finished = t >= sl.t_pub + 1e-6 * P->dry_us * sl.n;
-        } else {
-          const hipError_t qe = hipEventQuery(sl.done);
-          finished = qe != hipErrorNotReady;
-          if (finished && qe != hipSuccess) {
-            P->failed = true;
-            P->fail_detail = std::string("pipeline burst: ") + hipGetErrorString(qe);
-          }
-        }
-        if (finished)
-          complete(P, q.first, q.second, t);
-        else
-          still.push_back(q);
+    // completions: events polled without the lock
+    const double t = now_s();
+    finished.clear();
+    still.clear();
+    errs.clear();
+    for (auto& q : inflight) {
+      PipeSlot& sl = P->st[q.stream].slots[q.slot];
+      bool done;
+      if (P->dry) {
+        done = t >= sl.t_pub + 1e-6 * P->dry_us * sl.n;
+      } else {
+        const hipError_t qe = hipEventQuery(sl.done);
+        done = qe != hipErrorNotReady;
+        if (done && qe != hipSuccess) errs.push_back(qe);
       }
-      P->running.swap(still);
+      (done ? finished : still).push_back(q);
     }
-    if (!P->running.empty()) std::this_thread::yield();
+    inflight.swap(still);
+    if (!finished.empty() || !errs.empty()) {
+      std::lock_guard<std::mutex> lk(P->mu);
+      if (!errs.empty()) {
+        P->failed = true;
+        P->fail_detail = std::string("pipeline burst: ") + hipGetErrorString(errs.front());
+      }
+      for (auto& q : finished) complete(P, q, t);
+      P->in_flight -= (int64_t)finished.size();
+      P->cv.notify_all();
+    }
+    if (!inflight.empty()) std::this_thread::yield();
   }
 }
 
@@ -363,6 +439,11 @@ cg_status cg_pipeline_create(int32_t n_streams, cg_plan* const* plans, const uin
   P->st.resize(n_streams);
   hipError_t e = hipSuccess;
   if (!dry) e = hipGetDevice(&P->device);
+  if (!dry && e == hipSuccess) {
+    int khz = 0;
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, P->device);
+    if (e == hipSuccess && khz > 0) P->clk_hz = 1e3 * (double)khz;
+  }
   for (int i = 0; i < n_streams && e == hipSuccess; ++i) {
     PipeStream& ps = P->st[i];
     ps.slots.resize(slots_per_stream);
@@ -429,11 +510,10 @@ cg_status cg_pipeline_acquire(cg_pipeline* P, int32_t stream, int32_t* slot, int
   return CG_ERR_RING_FULL;
 }
 
-cg_status cg_pipeline_publish(cg_pipeline* P, int32_t stream, int32_t slot, int32_t n_frames,
-                              int64_t seq) {
-  if (!P) return CG_ERR_NULL;
-  if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
-  if (n_frames < 1 || n_frames > P->cap) return CG_ERR_INVALID_ARG;
+namespace {
+
+cg_status publish_burst(cg_pipeline* P, int32_t stream, int32_t slot, int32_t n_frames,
+                        int64_t seq, const void* src, size_t src_bytes) {
   {
     std::lock_guard<std::mutex> lk(P->mu);
     PipeStream& ps = P->st[stream];
@@ -442,13 +522,26 @@ cg_status cg_pipeline_publish(cg_pipeline* P, int32_t stream, int32_t slot, int3
     PipeSlot& sl = ps.slots[slot];
     sl.n = n_frames;
     sl.seq = seq;
+    sl.src = src;
+    sl.src_bytes = src_bytes;
     sl.t_pub = now_s();
     if (P->t_first < 0) P->t_first = sl.t_pub;
     sl.state = QUEUED;
-    P->queue.emplace_back(stream, slot);
+    if (P->keep) ps.published.push_back(slot);
+    P->queue.push_back(Burst{stream, slot});
   }
   P->cv.notify_all();
   return CG_OK;
+}
+
+}  // namespace
+
+cg_status cg_pipeline_publish(cg_pipeline* P, int32_t stream, int32_t slot, int32_t n_frames,
+                              int64_t seq) {
+  if (!P) return CG_ERR_NULL;
+  if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
+  if (n_frames < 1 || n_frames > P->cap) return CG_ERR_INVALID_ARG;
+  return publish_burst(P, stream, slot, n_frames, seq, nullptr, 0);
 }
 
 cg_status cg_pipeline_put(cg_pipeline* P, int32_t stream, const int16_t* src, int32_t n_frames,
@@ -458,19 +551,12 @@ cg_status cg_pipeline_put(cg_pipeline* P, int32_t stream, const int16_t* src, in
   if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
   if (n_frames < 1 || n_frames > P->cap) return CG_ERR_INVALID_ARG;
   int32_t slot = -1;
-  int16_t* dst = nullptr;
-  cg_status st = cg_pipeline_acquire(P, stream, &slot, &dst);
+  cg_status st = cg_pipeline_acquire(P, stream, &slot, nullptr);
   if (st != CG_OK) return st;
-  PipeStream& ps = P->st[stream];
-  // queued on the stream's own HIP stream, so it precedes the burst's graph
-  const hipError_t e = hipMemcpyAsync(dst, src, (size_t)n_frames * ps.plan->n * sizeof(int16_t),
-                                      hipMemcpyDefault, ps.hs);
-  if (e != hipSuccess) {
-    std::lock_guard<std::mutex> lk(P->mu);
-    ps.slots[slot].state = FREE;
-    return hip_fail(e, "cg_pipeline_put copy");
-  }
-  return cg_pipeline_publish(P, stream, slot, n_frames, seq);
+  // the dispatcher issues the copy on the stream's HIP stream ahead of the
+  // burst's graph
+  const size_t bytes = (size_t)n_frames * P->st[stream].plan->n * sizeof(int16_t);
+  return publish_burst(P, stream, slot, n_frames, seq, src, bytes);
 }
 
 cg_status cg_pipeline_read(cg_pipeline* P, int32_t stream, float* params, int32_t* status,
@@ -479,16 +565,18 @@ cg_status cg_pipeline_read(cg_pipeline* P, int32_t stream, float* params, int32_
   if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lk(P->mu);
   PipeStream& ps = P->st[stream];
-  if (ps.completed.empty()) {
+  // bursts are handed out in publish order: one that completed before an
+  // earlier one of its stream waits for it (the re-sort)
+  if (ps.published.empty() || ps.slots[ps.published.front()].state != DONE) {
     *n_frames = 0;
     return CG_ERR_STATE;
   }
-  const int j = ps.completed.front();
+  const int j = ps.published.front();
   PipeSlot& sl = ps.slots[j];
   if (sl.n > capacity) return CG_ERR_INVALID_ARG;
-  ps.completed.pop_front();
+  ps.published.pop_front();
   if (sl.seq <= ps.last_seq_read) {
-    cg::set_detail("results out of order");
+    cg::set_detail("sequence numbers of this stream were not increasing");
     sl.state = FREE;
     return CG_ERR_STATE;
   }
@@ -507,7 +595,7 @@ cg_status cg_pipeline_drain(cg_pipeline* P, int32_t timeout_ms) {
   if (!P) return CG_ERR_NULL;
   std::unique_lock<std::mutex> lk(P->mu);
   const bool ok = P->cv.wait_for(lk, std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms),
-                                 [&] { return P->queue.empty() && P->running.empty(); });
+                                 [&] { return P->queue.empty() && P->in_flight == 0; });
   if (P->failed) {
     cg::set_detail(P->fail_detail);
     return CG_ERR_HIP;
@@ -522,26 +610,38 @@ cg_status cg_pipeline_drain(cg_pipeline* P, int32_t timeout_ms) {
 cg_status cg_pipeline_stats(cg_pipeline* P, double* out, int32_t n_out) {
   if (!P || !out) return CG_ERR_NULL;
   if (n_out < CG_PIPE_NSTATS) return CG_ERR_INVALID_ARG;
-  std::vector<float> lat;
-  std::lock_guard<std::mutex> lk(P->mu);
-  lat = P->lat_ms;
-  auto pct = [&](double q) -> double {
-    if (lat.empty()) return 0.0;
-    const size_t i = std::min(lat.size() - 1, (size_t)(q * (double)(lat.size() - 1) + 0.5));
-    std::nth_element(lat.begin(), lat.begin() + i, lat.end());
-    return lat[i];
+  std::vector<float> lat, dlat, dspan;
+  double span;
+  {
+    std::lock_guard<std::mutex> lk(P->mu);
+    lat = P->lat_ms;
+    dlat = P->dev_lat_ms;
+    dspan = P->dev_span_ms;
+    span = P->t_first >= 0 ? P->t_last - P->t_first : 0.0;
+    out[0] = (double)P->bursts;
+    out[1] = (double)P->frames;
+    out[2] = P->bytes;
+    out[3] = (double)P->overflows;
+  }
+  auto pct = [](std::vector<float>& v, double q) -> double {
+    if (v.empty()) return 0.0;
+    const size_t i = std::min(v.size() - 1, (size_t)(q * (double)(v.size() - 1) + 0.5));
+    std::nth_element(v.begin(), v.begin() + i, v.end());
+    return v[i];
   };
-  const double span = P->t_first >= 0 ? P->t_last - P->t_first : 0.0;
-  out[0] = (double)P->bursts;
-  out[1] = (double)P->frames;
-  out[2] = P->bytes;
-  out[3] = (double)P->overflows;
+  auto vmax = [](const std::vector<float>& v) -> double {
+    return v.empty() ? 0.0 : (double)*std::max_element(v.begin(), v.end());
+  };
   out[4] = span;
-  out[5] = pct(0.5);
-  out[6] = pct(0.99);
-  out[7] = lat.empty() ? 0.0 : (double)*std::max_element(lat.begin(), lat.end());
-  out[8] = span > 0 ? P->bytes / span : 0.0;
-  out[9] = span > 0 ? (double)P->frames / span : 0.0;
+  out[5] = pct(lat, 0.5);
+  out[6] = pct(lat, 0.99);
+  out[7] = vmax(lat);
+  out[8] = span > 0 ? out[2] / span : 0.0;
+  out[9] = span > 0 ? out[1] / span : 0.0;
+  out[10] = pct(dlat, 0.5);
+  out[11] = pct(dlat, 0.99);
+  out[12] = vmax(dlat);
+  out[13] = pct(dspan, 0.5);
   return CG_OK;
 }
 
@@ -549,19 +649,42 @@ cg_status cg_autotune(cg_plan* p, const int16_t* frames, int64_t nf, uint32_t fl
                       void* workspace, size_t workspace_bytes, int32_t* chosen, float* best_ms) {
   if (!p || !frames || !chosen) return CG_ERR_NULL;
   if (nf < 1) return CG_ERR_INVALID_ARG;
-  const int cands[] = {4, 8, 16, 32, 64};
+  // candidate launch shapes: lanes per spectrum x spectra per wave in the fit,
+  // x the FFT grid (all resident blocks, or half of them)
+  struct Shape {
+    int lanes, chunk, fft;
+  };
+  std::vector<Shape> cands;
+  const int lane_opts[] = {8, 16};
+  const int chunk_mult[] = {1, 2, 4, 8};
+  const int fft_opts[] = {0, p->fft_blocks > 1 ? p->fft_blocks / 2 : 0};
+  for (int lanes : lane_opts) {
+    if (lanes == 8 && p->k > 224) continue;
+    for (int cm : chunk_mult)
+      for (int fi = 0; fi < 2; ++fi) {
+        if (fi == 1 && fft_opts[1] == 0) continue;
+        cands.push_back(Shape{lanes, (64 / lanes) * cm, fft_opts[fi]});
+      }
+  }
   float* params = nullptr;
   hipError_t e = hipMalloc(&params, (size_t)nf * 16);
   if (e != hipSuccess) return hip_fail(e, "autotune alloc");
-  hipEvent_t a, b;
-  (void)hipEventCreate(&a);
-  (void)hipEventCreate(&b);
-  const int32_t saved = p->lm_chunk;
+  hipEvent_t a = nullptr, b = nullptr;
+  e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    (void)hipFree(params);
+    return hip_fail(e, "autotune events");
+  }
+  const int32_t saved[3] = {p->lm_lanes, p->lm_chunk, p->fft_cap};
   float best = 1e30f;
-  int32_t pick = 0;
+  Shape pick = {saved[0], saved[1], saved[2]};
   cg_status st = CG_OK;
-  for (int c : cands) {
-    p->lm_chunk = c;
+  for (const Shape& c : cands) {
+    p->lm_lanes = c.lanes;
+    p->lm_chunk = c.chunk;
+    p->fft_cap = c.fft;
     // one untimed pass, then three timed ones
     for (int r = 0; r < 4 && st == CG_OK; ++r) {
       if (r == 1) (void)hipEventRecord(a, nullptr);
@@ -583,11 +706,15 @@ cg_status cg_autotune(cg_plan* p, const int16_t* frames, int64_t nf, uint32_t fl
   (void)hipEventDestroy(b);
   (void)hipFree(params);
   if (st != CG_OK) {
-    p->lm_chunk = saved;
+    p->lm_lanes = saved[0];
+    p->lm_chunk = saved[1];
+    p->fft_cap = saved[2];
     return st;
   }
-  p->lm_chunk = pick;
-  *chosen = pick;
+  p->lm_lanes = pick.lanes;
+  p->lm_chunk = pick.chunk;
+  p->fft_cap = pick.fft;
+  *chosen = pick.chunk;
   if (best_ms) *best_ms = best;
   return CG_OK;
 }

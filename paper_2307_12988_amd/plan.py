@@ -25,6 +25,8 @@ FIT_NONE = 0x20
 
 FIT_CONVERGED, FIT_MAX_ITER, FIT_SINGULAR, FIT_FALLBACK = 0, 1, 2, 3
 TUNE_LM_CHUNK = 1
+TUNE_LM_LANES = 2
+TUNE_FFT_BLOCKS = 3
 MLP_NPARAMS = 123396
 MLP_IN = 220
 
@@ -247,9 +249,21 @@ class Plan:
         _lib.check(st, "cg_mlp_infer")
         return out
 
+    def get_tuning(self, knob: int) -> int:
+        v = ctypes.c_int32()
+        _lib.check(self._lib.cg_get_tuning(self._h, int(knob), ctypes.byref(v)), "cg_get_tuning")
+        return v.value
+
+    def tuned_shape(self):
+        """The plan's launch shape: fit lanes per spectrum, spectra per
+        wavefront and FFT grid cap (0 = chosen automatically)."""
+        return {"lm_lanes": self.get_tuning(TUNE_LM_LANES),
+                "lm_chunk": self.get_tuning(TUNE_LM_CHUNK),
+                "fft_blocks": self.get_tuning(TUNE_FFT_BLOCKS)}
+
     def autotune(self, frames, flags: int = 0):
-        """Pick the fastest fit-kernel launch shape for these frames; returns
-        (spectra per wavefront, ms per batch)."""
+        """Pick the fastest launch shape for these frames (see cg_autotune);
+        returns (spectra per wavefront, ms per batch)."""
         nf, fp = self._frames(frames)
         chosen = ctypes.c_int32()
         best = ctypes.c_float()
@@ -366,7 +380,8 @@ class Trainer:
 PIPE_KEEP_RESULTS = 0x1
 PIPE_DRY_RUN = 0x2
 STATS_FIELDS = ("bursts", "frames", "bytes", "overflows", "seconds", "lat_p50_ms", "lat_p99_ms",
-                "lat_max_ms", "bytes_per_s", "frames_per_s")
+                "lat_max_ms", "bytes_per_s", "frames_per_s", "dev_lat_p50_ms", "dev_lat_p99_ms",
+                "dev_lat_max_ms", "dev_span_p50_ms")
 
 
 class RingFull(_lib.CombGpuError):
