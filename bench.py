@@ -7,9 +7,10 @@ samples (1.1 GS/s, i.e. 2.2 GB/s of int16 per stream), 220 comb teeth,
 per-frame dip FWHM U[4,16] teeth and SNR U[20,50] dB, cold-start 7x7-median
 start point and Levenberg-Marquardt fit.  A step is one pass of the whole
 path (ingest, FFT, tooth gather, normalisation, median start point, fit) over
-one batch.  A pool of distinct batches (1 GiB, four times the 256 MB
+one batch.  A pool of 16 distinct batches (4 GiB, sixteen times the 256 MB
 last-level cache) is resident in HBM before timing starts and is cycled
-through.  Prints one JSON line.
+through.  After the K timed steps a sustained leg runs the same steps for at
+least 60 s (extra keys).  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -96,6 +97,33 @@ def make_pool(spec, nf, n_batches, workers, truth=False):
     return (frames, ref, truths) if truth else (frames, ref)
 
 
+def lm_flops_fp32_basis(k, iters):
+    """Algorithmic work of the fit by the FP32-vector count: about 50 K flops
+    per LM iteration for the model, Jacobian and normal equations over K teeth
+    plus about 100 for the damped 4x4 solve."""
+    iters = np.asarray(iters, dtype=np.float64)
+    return float(np.sum(iters)) * (50.0 * k + 100.0)
+
+
+def host_info():
+    """Host CPU description for the CPU-baseline record."""
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:  # pragma: no cover
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:  # pragma: no cover
+        affinity = None
+    return {"cpu_count": os.cpu_count(), "affinity_cpus": affinity, "model": model}
+
+
 def lm_flops(k, iters):
     """Algorithmic work of the fit, (FP32 flops, FP64 flops): per tooth and
     evaluation the model, residual and chi2 take about 14 FP64 flops and the
@@ -116,7 +144,10 @@ def mixed_peak_tflops(f32, f64):
 
 def cpu_baseline(spec, frames, gpu_params, ref_frames, n_sample):
     """Time the FP64 oracle on a contiguous slice of the first batch and
-    compare its centres with the GPU's for the same frames."""
+    compare its centres with the GPU's for the same frames.  The stages are
+    timed separately: the DFT at the teeth is a BLAS matrix product (BLAS
+    threads), the 7x7 median, start points and the per-frame LM loop run on
+    one Python thread."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -126,13 +157,19 @@ def cpu_baseline(spec, frames, gpu_params, ref_frames, n_sample):
     sl = frames[:n_sample]
     t0 = time.perf_counter()
     ref = oracle.reference_spectrum(ref_frames, spec.bins)
-    out = oracle.process_batch(sl, spec.bins, ref)
-    dt = time.perf_counter() - t0
+    mags = oracle.tooth_magnitudes(sl, spec.bins)
+    t1 = time.perf_counter()
+    y = oracle.normalize(mags, ref)
+    p0 = oracle.initial_guess(y)
+    t2 = time.perf_counter()
+    params, iters, status, chi2 = oracle.lm_fit_batch(y, p0)
+    t3 = time.perf_counter()
+    dt = t3 - t0
     # the oracle replicates the slice's last frame where the GPU saw the next
     # frames of the batch: compare away from that edge
     m = n_sample - 3
-    err = np.abs(gpu_params[:m, 0] - out["params"][:m, 0]) / np.abs(out["params"][:m, 1])
-    conv = out["status"][:m] == 0
+    err = np.abs(gpu_params[:m, 0] - params[:m, 0]) / np.abs(params[:m, 1])
+    conv = status[:m] == 0
     frac = float(np.mean(err[conv] <= 1e-3)) if conv.any() else 0.0
     gbs = n_sample * spec.n * 2 / dt / 1e9
     return {
@@ -142,8 +179,11 @@ def cpu_baseline(spec, frames, gpu_params, ref_frames, n_sample):
         "cores": int(threads),
         "kind": "oracle",
         "sample": f"first {n_sample} frames of batch 0 of the same stream (FP64 DFT at the "
-                  f"teeth via BLAS matmul, 7x7 median, per-frame LM loop in Python), "
-                  f"{dt:.1f} s",
+                  f"teeth via BLAS matmul on {threads} threads, then 7x7 median, start points "
+                  f"and the per-frame LM loop on one Python thread), {dt:.1f} s",
+        "stage_seconds": {"dft_blas": t1 - t0, "median_start_1thread": t2 - t1,
+                          "lm_1thread": t3 - t2},
+        "host": host_info(),
         "parity_vs_gpu": {"frames": int(conv.sum()), "centre_within_1e-3_fwhm": frac,
                           "max_err_fwhm": float(err[conv].max()) if conv.any() else None},
     }
@@ -332,6 +372,68 @@ def warm_forms(args, torch, cg, dev):
     plan.close()
 
 
+def multistream_parity(args, torch, cg, dev, specs, plans, pools, gen, w, tune):
+    """Accuracy leg of the multi-stream workload: two bursts per stream
+    through a pipeline that keeps its results, and a fixed 1-in-64 frame
+    sample of every burst compared with the FP64 oracle's warm path (same
+    network, same noise floor) and with the oracle's cold-start fit."""
+    import oracle
+    from oracle.pipeline import network_start, warm_fit
+    _log("multistream parity leg (oracle on a 1-in-64 sample) ...")
+    ns = len(specs)
+    pipe = cg.Pipeline(plans, [cg.FIT_WARM_MLP] * ns, slots_per_stream=2, max_burst_frames=4096,
+                       keep_results=True)
+    rng = np.random.default_rng(17)
+    sent = []
+    for s in range(ns):
+        for j in range(2):
+            n = int(rng.integers(256, 4097))
+            off = 4096 * j
+            pipe.put(s, pools[s][off:off + n], j)
+            sent.append((s, j, off, n))
+    pipe.drain(120000)
+    got = {}
+    for s in range(ns):
+        for j in range(2):
+            r = pipe.read(s)
+            got[(s, j)] = r[1]
+    pipe.close()
+    ok_w = ok_c = total = 0
+    worst = 0.0
+    t0 = time.perf_counter()
+    for s, j, off, n in sent:
+        sp = specs[s]
+        frames = gen[s][1][off:off + n]
+        ref = _plan_ref(plans[s], torch)
+        y = oracle.normalize(oracle.tooth_magnitudes(frames, sp.bins), ref)
+        rows = np.arange(j % 64, n, 64)
+        p0 = network_start(y[rows], w["params"].astype(np.float64), w["out_mean"], w["out_std"])
+        par, _, stat, c2, _ = warm_fit(y, p0, tune[s]["noise_floor"], rows=rows)
+        cold = oracle.lm_fit_batch(y[rows], oracle.initial_guess(y)[rows])
+        g = got[(s, j)][rows]
+        ew = np.abs(g[:, 0] - par[:, 0]) / np.abs(par[:, 1])
+        ec = np.abs(g[:, 0] - cold[0][:, 0]) / np.abs(cold[0][:, 1])
+        okw = ew <= 1e-3
+        # an equally good minimum (FP64 chi2 at the GPU's point within 1e-6)
+        for f in np.nonzero(~okw)[0]:
+            if np.all(np.isfinite(g[f])) and g[f, 1] > 0:
+                okw[f] = oracle.chi2_at(y[rows[f]], g[f]) <= c2[f] * (1 + 1e-6)
+        ok_w += int(okw.sum())
+        ok_c += int(np.count_nonzero(ec <= 1e-3))
+        total += rows.size
+        worst = max(worst, float(ew.max()))
+    return {"sample": "every 64th frame of two bursts per stream", "frames": total,
+            "within_1e-3_fwhm_of_oracle_warm_path": ok_w / max(total, 1),
+            "max_err_fwhm_vs_oracle_warm_path": worst,
+            "within_1e-3_fwhm_of_oracle_cold_fit": ok_c / max(total, 1),
+            "oracle_seconds": time.perf_counter() - t0}
+
+
+def _plan_ref(plan, torch):
+    """The plan's installed reference spectrum (host copy kept by the bench)."""
+    return plan._bench_ref
+
+
 def multistream(args, torch, cg, dev):
     """16 concurrent streams (frame lengths 512..8192, 64..440 teeth, own
     reference, dip parameters and noise floor) through the ring pipeline with
@@ -351,7 +453,9 @@ def multistream(args, torch, cg, dev):
     tune = {}
     for i, (sp, (_, frames, ref_frames, _truth)) in enumerate(zip(specs, gen)):
         pl = cg.Plan(sp.n, sp.fs, sp.bins, np.ones(sp.k, dtype=np.float32))
-        pl.set_reference(pl.reference_from_frames(torch.from_numpy(ref_frames).to(dev)).cpu().numpy())
+        ref_s = pl.reference_from_frames(torch.from_numpy(ref_frames).to(dev)).cpu().numpy()
+        pl.set_reference(ref_s)
+        pl._bench_ref = ref_s
         pool = torch.from_numpy(frames).to(dev)
         # per-stream noise floor from a cold-start calibration batch (host median)
         cal = pl.process(pool[:2048], want=("params", "status", "chi2"))
@@ -360,14 +464,40 @@ def multistream(args, torch, cg, dev):
         noise = float(np.median(np.sqrt(np.maximum(c2[ok], 0) / (sp.k - 4))))
         pl.set_mlp(w["params"], w["out_mean"], w["out_std"], noise)
         chunk, ms = pl.autotune(pool[:4096], flags=cg.FIT_WARM_MLP)
-        tune[i] = {"n": sp.n, "k": sp.k, "lm_chunk": chunk, "ms_4096": ms, "noise_floor": noise}
+        tune[i] = {"n": sp.n, "k": sp.k, **pl.tuned_shape(), "ms_4096": ms, "noise_floor": noise}
         plans.append(pl)
         pools.append(pool)
         fl.append(cg.FIT_WARM_MLP)
     torch.cuda.synchronize(dev)
+    ns = len(specs)
+    # per stream class: the FFT stage's HBM roofline on one 4096-frame burst
+    classes = {}
+    for i, sp in enumerate(specs):
+        pl = plans[i]
+        y = torch.empty((4096, sp.k), dtype=torch.float32, device=dev)
+        pl.teeth(pools[i][:4096], want_mag=False, want_y=True, out_y=y)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        stream = torch.cuda.current_stream(dev)
+        ev[0].record(stream)
+        for r in range(5):
+            off = 4096 * (r % 2)
+            pl.teeth(pools[i][off:off + 4096], want_mag=False, want_y=True, out_y=y)
+        ev[1].record(stream)
+        torch.cuda.synchronize(dev)
+        t = ev[0].elapsed_time(ev[1]) / 5 * 1e-3
+        gbs = 4096 * (2 * sp.n + 4 * sp.k) / t / 1e9
+        c = classes.setdefault(str(sp.n), {"streams": 0, "fft_GBps": []})
+        c["streams"] += 1
+        c["fft_GBps"].append(gbs)
+    for c in classes.values():
+        c["fft_GBps_mean"] = float(np.mean(c["fft_GBps"]))
+        c["fft_frac_of_hbm_peak"] = c["fft_GBps_mean"] / HBM_PEAK_GBS
+        c["fft_GBps"] = [round(v, 1) for v in c["fft_GBps"]]
+    parity = None
+    if not args.no_cpu_baseline:
+        parity = multistream_parity(args, torch, cg, dev, specs, plans, pools, gen, w, tune)
     pipe = cg.Pipeline(plans, fl, slots_per_stream=args.slots, max_burst_frames=4096)
     rng = np.random.default_rng(7)
-    ns = len(specs)
 
     def burst(i):
         n = int(rng.integers(256, 4097))
@@ -435,9 +565,16 @@ def multistream(args, torch, cg, dev):
                          "achieved_GBps": s2["bytes_per_s"] / 1e9, "dropped_bursts": dropped,
                          "overflows": s2["overflows"], "lat_p50_ms": s2["lat_p50_ms"],
                          "lat_p99_ms": s2["lat_p99_ms"], "lat_max_ms": s2["lat_max_ms"],
+                         "dev_lat_p50_ms": s2["dev_lat_p50_ms"],
+                         "dev_lat_p99_ms": s2["dev_lat_p99_ms"],
+                         "dev_lat_max_ms": s2["dev_lat_max_ms"],
+                         "dev_span_p50_ms": s2["dev_span_p50_ms"],
                          "bursts": s2["bursts"]},
         "autotune": tune,
+        "stream_classes": classes,
     }
+    if parity is not None:
+        line["parity"] = parity
     print(json.dumps(line), flush=True)
     for pl in plans:
         pl.close()
@@ -448,7 +585,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--pool", type=int, default=4, help="distinct batches resident in HBM")
+    ap.add_argument("--pool", type=int, default=16, help="distinct batches resident in HBM")
+    ap.add_argument("--sustain", type=float, default=60.0,
+                    help="paper-rate: seconds of the sustained leg after the timed steps "
+                         "(0 = skip)")
     ap.add_argument("--streams", type=int, default=3,
                     help="paper-rate: HIP streams that consecutive batches alternate over")
     ap.add_argument("--frames", type=int, default=65536)
@@ -508,8 +648,10 @@ def main():
     _log(f"generating {args.pool} batches of {nf} x {n} int16 ...")
     t0 = time.perf_counter()
     pool_np, ref_np = make_pool(spec, nf, args.pool, workers=min(args.pool, 8))
+    pool_np_0 = pool_np[0]
     _log(f"  {time.perf_counter() - t0:.1f} s")
     pool = [torch.from_numpy(fr).to(dev) for fr in pool_np]
+    del pool_np
     ref_frames = torch.from_numpy(ref_np).to(dev)
 
     plan = cg.Plan(n, spec.fs, spec.bins, np.ones(k, dtype=np.float32))
@@ -554,6 +696,45 @@ def main():
     it_np = iters.cpu().numpy()
     st_np = status.cpu().numpy()
 
+    sustained = None
+    if args.sustain > 0:
+        # the same steps for at least args.sustain seconds, cycling over the
+        # pool; every batch's parameters are checked at the end against the
+        # first pass over the pool (the path is deterministic)
+        _log(f"sustained leg: {args.sustain:.0f} s ...")
+        first = {}
+        for b in range(len(pool)):
+            step(b * ns)          # on stream 0, pool batch (b * ns) mod pool size
+            torch.cuda.synchronize(dev)
+            first[b] = outs[0][0].clone()
+        done = 0
+        chunk = 256
+        t0 = time.perf_counter()
+        last = t0
+        while True:
+            for i in range(chunk):
+                step(done + i)
+            done += chunk
+            torch.cuda.synchronize(dev)
+            now = time.perf_counter()
+            if now - last >= 10.0:
+                _log(f"  {now - t0:.0f} s: {done} batches")
+                last = now
+            if now - t0 >= args.sustain:
+                break
+        swall = time.perf_counter() - t0
+        same = True
+        for b in range(len(pool)):
+            step(b * ns)
+            torch.cuda.synchronize(dev)
+            same = same and bool(torch.equal(outs[0][0], first[b]))
+        sustained = {"seconds": swall, "batches": done,
+                     "GBps": nf * n * 2 * done / swall / 1e9,
+                     "spectra_per_s": nf * done / swall,
+                     "ms_per_batch": swall / done * 1e3,
+                     "outputs_identical_to_first_pass": same}
+        del first
+
     # per-kernel durations: the same three kernels, one entry point each, with
     # events on the stream they are launched on
     _log("per-kernel timing ...")
@@ -587,11 +768,16 @@ def main():
         ev[1].record(stream)
         torch.cuda.synchronize(dev)
         acc[nm] = ev[0].elapsed_time(ev[1])
-    f32, f64 = lm_flops(k, iters.cpu().numpy())
-    flops = reps * (f32 + f64)
+    it_fit = iters.cpu().numpy()
+    f32, f64 = lm_flops(k, it_fit)
     lm_peak = mixed_peak_tflops(f32, f64)
     ms = {nm: acc[nm] / reps for nm in names}
-    lm_tflops = flops / (acc["lm_fit"] * 1e-3) / 1e12
+    # the fit's roofline by the FP32-vector count (about 50 K + 100 flops per
+    # iteration) against the published FP32 vector peak; the count of the
+    # kernel's own FP32/FP64 mix against the matching mixed peak is kept as a
+    # secondary figure
+    lm_tflops = reps * lm_flops_fp32_basis(k, it_fit) / (acc["lm_fit"] * 1e-3) / 1e12
+    lm_mix_tflops = reps * (f32 + f64) / (acc["lm_fit"] * 1e-3) / 1e12
     fft_bytes = nf * (2 * n + 4 * k)
     med_ops = MEDIAN_OPS_PER_OUTPUT * nf * k
     stages = {
@@ -600,7 +786,10 @@ def main():
                       "frac_of_hbm_peak": fft_bytes / (ms["fft_teeth"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "median_start": {"ms": ms["median_start"], "bound": "alu",
                          "achieved_Tops": med_ops / (ms["median_start"] * 1e-3) / 1e12},
-        "lm_fit": {"ms": ms["lm_fit"], "bound": "alu", "achieved_TFLOPs": lm_tflops},
+        "lm_fit": {"ms": ms["lm_fit"], "bound": "alu", "achieved_TFLOPs": lm_tflops,
+                   "frac_of_fp32_peak": lm_tflops / VALU_FP32_PEAK_TFLOPS,
+                   "mix_count_TFLOPs": lm_mix_tflops, "mix_peak_TFLOPs": lm_peak,
+                   "mix_frac": lm_mix_tflops / lm_peak},
     }
     dom = max(names, key=lambda nm: ms[nm])
     if dom == "fft_teeth":
@@ -609,9 +798,10 @@ def main():
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic_bytes(dom)}
     elif dom == "lm_fit":
         roof = {"kernel": dom, "bound": "alu", "achieved": lm_tflops,
-                "peak": lm_peak, "unit": "TFLOP/s",
-                "frac": lm_tflops / lm_peak, "traffic": traffic_bytes(dom),
-                "peak_basis": "FP32 + FP64 mix of the fit at the published vector peaks"}
+                "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": lm_tflops / VALU_FP32_PEAK_TFLOPS, "traffic": traffic_bytes(dom),
+                "flop_count": "sum over frames of LM iterations x (50 K + 100)",
+                "mix_count_frac": lm_mix_tflops / lm_peak}
     else:
         ach = med_ops / (ms[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": VALU_OPS_PEAK_TOPS,
@@ -634,18 +824,21 @@ def main():
         "config": {"workload": f"paper-rate comb stream: {nf} frames x {n} int16 samples per "
                                f"batch, {k} teeth, cold-start 7x7 median + LM (<=20 it)",
                    "frames_per_batch": nf, "frame_len": n, "n_teeth": k,
-                   "pool_batches": args.pool, "streams": ns},
+                   "pool_batches": args.pool, "pool_GiB": args.pool * nf * n * 2 / 2 ** 30,
+                   "streams": ns},
         "spectra_per_s": sps,
         "fit": {"mean_iters": float(it_np.mean()), "converged_frac": float(np.mean(st_np == 0)),
                 "status_counts": np.bincount(st_np, minlength=4).tolist()},
         "stages": stages,
         "roofline": roof,
     }
+    if sustained is not None:
+        result["sustained"] = sustained
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle) ...")
         plan.process(pool[0], params=params, iters=iters, status=status, workspace=ws, want=())
         torch.cuda.synchronize(dev)
-        result["cpu_baseline"] = cpu_baseline(spec, pool_np[0], params.cpu().numpy(), ref_np,
+        result["cpu_baseline"] = cpu_baseline(spec, pool_np_0, params.cpu().numpy(), ref_np,
                                               args.cpu_frames)
     print(json.dumps(result), flush=True)
     plan.close()

@@ -294,7 +294,9 @@ cg_status cg_mlp_gradients(cg_mlp_trainer* trainer, const float* x, const float*
 cg_status cg_mlp_get_params(cg_mlp_trainer* trainer, float* params);
 
 /*
- * Tuning knobs of a plan (launch shapes only; results do not depend on them).
+ * Tuning knobs of a plan (launch shapes only).  Spectra per wavefront and the
+ * FFT grid do not change any result; lanes per spectrum changes the order in
+ * which each spectrum's sums are reduced, so results move by rounding only.
  *   CG_TUNE_LM_CHUNK    spectra per wavefront in the fit kernel: 0 = chosen
  *                       from the batch size (default), else a multiple of 4 in
  *                       4..256.

@@ -44,15 +44,20 @@ def network_start(y, params, out_mean, out_std):
     return p0
 
 
-def warm_fit(y, p0, noise_floor, polish_iter: int = 2, max_iter: int = 20, tol: float = 1e-6):
+def warm_fit(y, p0, noise_floor, polish_iter: int = 2, max_iter: int = 20, tol: float = 1e-6,
+             rows=None):
     """Polish each spectrum from its warm start point p0 by `polish_iter` LM
     iterations; a frame whose RMS residual sqrt(chi2 / (K - 4)) then exceeds
     2 * noise_floor (or is not finite) is fitted again from the cold start
-    point (7x7 median) with up to `max_iter` iterations and gets status 3.
-    Its reported iteration count is the refit's.  Returns (params, iters,
-    status, chi2, fell_back)."""
+    point (7x7 median over the whole batch y) with up to `max_iter`
+    iterations and gets status 3.  Its reported iteration count is the
+    refit's.  With `rows`, only those frames of y are fitted (p0 then holds
+    their start points, in that order).  Returns (params, iters, status,
+    chi2, fell_back) for the fitted frames."""
     y = np.asarray(y, dtype=np.float64)
-    f_count, k = y.shape
+    k = y.shape[1]
+    rows = np.arange(y.shape[0]) if rows is None else np.asarray(rows)
+    f_count = rows.shape[0]
     cold_p0 = None
     params_out = np.empty((f_count, 4))
     iters = np.empty(f_count, dtype=np.int32)
@@ -61,15 +66,15 @@ def warm_fit(y, p0, noise_floor, polish_iter: int = 2, max_iter: int = 20, tol: 
     fell = np.zeros(f_count, dtype=bool)
     # RMS residual > 2 sigma  <=>  chi2 > 4 sigma^2 (K - 4)
     thr2 = 4.0 * noise_floor ** 2 * max(k - 4, 1)
-    for f in range(f_count):
-        p, it, st, c2 = lm_fit(y[f], p0[f], polish_iter, tol)
+    for j, f in enumerate(rows):
+        p, it, st, c2 = lm_fit(y[f], p0[j], polish_iter, tol)
         if not np.isfinite(c2) or c2 > thr2:
             if cold_p0 is None:
                 cold_p0 = initial_guess(y)
             p, it, st, c2 = lm_fit(y[f], cold_p0[f], max_iter, tol)
             st = STATUS_FALLBACK
-            fell[f] = True
-        params_out[f], iters[f], status[f], chi2[f] = p, it, st, c2
+            fell[j] = True
+        params_out[j], iters[j], status[j], chi2[j] = p, it, st, c2
     return params_out, iters, status, chi2, fell
 
 

@@ -1,9 +1,25 @@
-"""Learned warm start on the GPU against the FP64 oracle (bfloat16 operand
-rounding emulated at the same points).  Bars: gradients and forward outputs
-agree to 2e-3 in norm per tensor (rare bf16 rounding flips of intermediate
-operands move single elements by 2^-8); one Adam step moves every parameter
-within 1e-5 of the oracle's move; the warm path's centres meet the 1e-3 FWHM
-bar against the oracle's warm path."""
+"""Learned warm start on the GPU against the FP64 oracle.
+
+Bars, element by element.  For an element e of a product sum_s a_s b_s
+(a gradient entry, an output) let S_e = sum_s |a_s b_s| over the oracle's
+operands.
+* Against the oracle with bfloat16 operand rounding emulated at the kernels'
+  rounding points: |gpu - oracle| <= 2^-9 S_e for every element.  FP32
+  accumulation of <= 512 terms is within 512 * 2^-24 = 2^-15 S_e; what can
+  exceed it is a bfloat16 operand that rounds the other way because its FP32
+  input differs in the last bits from the FP64 one (one flip moves one term by
+  one bfloat16 step, <= 2^-7 of it).  Such elements are counted: at most 1 %
+  of a tensor's elements may exceed 2^-12 S_e.
+* Against the plain FP64 network (no bfloat16 rounding): |gpu - oracle| <=
+  2^-4 S_e per element and 2^-5 in norm per tensor.  Each rounded operand is
+  within 2^-9 of its value; a gradient of W1 passes through up to seven
+  rounding stages (x, W1, a1, W2, a2, W3 and the output gradient) whose
+  errors add in proportion to S_e: 7 * 2 * 2^-9 ~ 2^-5.2, doubled for the
+  products of two such operands.  Forward outputs: three stages, 2^-6.
+* One Adam step moves every parameter with a clear gradient within 1e-5 of
+  the oracle's move.
+* Warm-path centres: the 1e-3 FWHM bar of the plain path, against the
+  oracle's warm path, on >= 99.9 % of frames."""
 
 import os
 import sys
@@ -33,12 +49,38 @@ def _say(m):
     sys.stdout.flush()
 
 
-def _tensor_errors(a, b):
-    errs = {}
+def _grad_scales(x, t, p, w, bf16_ops):
+    """Per-element S_e = sum of |products| of each gradient entry, from the
+    oracle's own operands (flat layout)."""
+    out, cache = omlp.forward(x, p, bf16_ops)
+    _, dout = omlp.loss_and_dout(out, t, w)
+    r, P = cache["r"], cache["p"]
+    d3 = r(dout)
+    dh2 = (d3 @ r(P["W3"])) * omlp.gelu_grad(cache["h2"])
+    dh2q = r(dh2)
+    dh1 = (dh2q @ r(P["W2"])) * omlp.gelu_grad(cache["h1"])
+    dh1q = r(dh1)
+    s = {"W3": np.abs(d3).T @ np.abs(cache["a2q"]), "b3": np.abs(dout).sum(0),
+         "W2": np.abs(dh2q).T @ np.abs(cache["a1q"]), "b2": np.abs(dh2).sum(0),
+         "W1": np.abs(dh1q).T @ np.abs(cache["xq"]), "b1": np.abs(dh1).sum(0)}
+    return omlp.pack(s)
+
+
+def _elementwise(got, want, scale, tight, loose, max_frac_over_tight, norm_bar=None):
+    """Per-tensor element-wise check; returns a report dict."""
+    rep = {}
     for name, _ in omlp.SHAPES:
-        ua, ub = omlp.unpack(a)[name], omlp.unpack(b)[name]
-        errs[name] = float(np.linalg.norm(ua - ub) / max(np.linalg.norm(ub), 1e-30))
-    return errs
+        g, o, sc = (omlp.unpack(a)[name].ravel() for a in (got, want, scale))
+        rel = np.abs(g - o) / np.maximum(sc, 1e-30)
+        over = int(np.count_nonzero(rel > tight))
+        nrm = float(np.linalg.norm(g - o) / max(np.linalg.norm(o), 1e-30))
+        rep[name] = {"max_rel_to_S": float(rel.max()), "over_tight": over, "n": int(rel.size),
+                     "norm": nrm}
+        assert rel.max() <= loose, (name, rep[name])
+        assert over <= max_frac_over_tight * rel.size, (name, rep[name])
+        if norm_bar is not None:
+            assert nrm <= norm_bar, (name, rep[name])
+    return rep
 
 
 def _data(n, seed):
@@ -59,11 +101,17 @@ def test_gradients_match_oracle():
     g, loss = tr.gradients(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV),
                            torch.from_numpy(w).to(DEV), torch.from_numpy(idx).to(DEV))
     torch.cuda.synchronize()
-    lo, go = omlp.loss_and_grads(x[idx].astype(np.float64), t[idx], p.astype(np.float64), w[idx])
-    errs = _tensor_errors(g.cpu().numpy().astype(np.float64), go)
-    _say(f"grad errors {errs}, loss {loss.item():.6f} vs {lo:.6f}")
+    xs, ts, ws = x[idx].astype(np.float64), t[idx].astype(np.float64), w[idx].astype(np.float64)
+    pd = p.astype(np.float64)
+    gg = g.cpu().numpy().astype(np.float64)
+    lo, go = omlp.loss_and_grads(xs, ts, pd, ws)
+    rep = _elementwise(gg, go, _grad_scales(xs, ts, pd, ws, True), 2.0 ** -12, 2.0 ** -9, 0.01)
+    _say(f"grads vs bf16 oracle: {rep}, loss {loss.item():.6f} vs {lo:.6f}")
     assert abs(loss.item() - lo) <= 1e-4 * abs(lo)
-    assert max(errs.values()) <= 2e-3, errs
+    lo64, go64 = omlp.loss_and_grads(xs, ts, pd, ws, bf16_ops=False)
+    rep64 = _elementwise(gg, go64, _grad_scales(xs, ts, pd, ws, False), 2.0 ** -4, 2.0 ** -4,
+                         0.0, norm_bar=2.0 ** -5)
+    _say(f"grads vs plain FP64 oracle: {rep64}")
 
 
 def test_adam_step_matches_oracle():
@@ -95,19 +143,27 @@ def test_infer_matches_oracle_forward(k):
     plan = cg.Plan(2048 if k <= 440 else 4096, 1e9, np.arange(1, k + 1), np.ones(k))
     plan.set_mlp(p, mean, std, 0.01)
     got = plan.mlp_infer(torch.from_numpy(y).to(DEV)).cpu().numpy().astype(np.float64)
-    z, _ = omlp.forward(omlp.resample_to_input(y.astype(np.float64)), p.astype(np.float64))
-    want = z * std + mean
-    want[:, :2] *= (k - 1) / 219
-    rel = np.linalg.norm(got - want, axis=0) / np.linalg.norm(want, axis=0)
-    zerr = np.linalg.norm((got - want) / std, axis=0) / np.linalg.norm(z, axis=0)
-    _say(f"k={k}: rel {rel}, standardised {zerr}")
-    assert np.all(zerr <= 2e-3)
+    xin = omlp.resample_to_input(y.astype(np.float64))
+    scale = std.astype(np.float64) * np.array([(k - 1) / 219, (k - 1) / 219, 1.0, 1.0])
+    for bf16_ops, tight, loose, frac in ((True, 2.0 ** -12, 2.0 ** -9, 0.01),
+                                         (False, 2.0 ** -6, 2.0 ** -6, 0.0)):
+        z, cache = omlp.forward(xin, p.astype(np.float64), bf16_ops=bf16_ops)
+        want = (z * std + mean) * np.array([(k - 1) / 219, (k - 1) / 219, 1.0, 1.0])
+        r = cache["r"]
+        # S_e of the last layer's sum, in the output's units
+        s_e = (np.abs(cache["a2q"]) @ np.abs(r(cache["p"]["W3"])).T
+               + np.abs(cache["p"]["b3"])) * scale
+        rel = np.abs(got - want) / s_e
+        over = int(np.count_nonzero(rel > tight))
+        _say(f"k={k} bf16_ops={bf16_ops}: max |err|/S {rel.max():.3e}, over {over} of {rel.size}")
+        assert rel.max() <= loose
+        assert over <= frac * rel.size
 
 
 def test_warm_path_matches_oracle_with_random_network():
     """An untrained network puts most frames on the fallback path."""
     spec = synth.spec_learned()
-    bt = synth.make_batch(spec, 300, seed=8)
+    bt = synth.make_batch(spec, 1200, seed=8)
     ref = oracle.reference_spectrum(bt.ref_frames, spec.bins).astype(np.float32)
     p = train_mlp.he_init(1)
     mean = np.array([109.5, 10.0, 0.5, 1.0], dtype=np.float32)
@@ -125,7 +181,8 @@ def test_warm_path_matches_oracle_with_random_network():
     assert np.mean(st == ora["status"]) >= 0.99
     res = centre_parity(ora["y"], out["params"].cpu().numpy(), ora["params"],
                         np.where(ora["status"] == 3, 0, ora["status"]), ora["chi2"])
-    assert res["fraction"] >= 0.99, res
+    _say(f"  parity {res['fraction']:.5f} of {res['n']}, exempt {res['exempt']}")
+    assert res["fraction"] >= PASS_FRACTION, res
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not built")
@@ -151,8 +208,20 @@ def test_warm_path_with_trained_network():
          f"{cold['iters'].float().mean().item():.2f}")
     assert res["fraction"] >= PASS_FRACTION, res
     assert np.mean(st == 3) < 0.2
-    # the gain over the method without the network: fewer LM iterations per frame
-    assert warm["iters"].float().mean().item() < cold["iters"].float().mean().item()
+    # what the network gains over the method without it: a start point much
+    # closer to where the cold-start fit converges than the 7x7-median start
+    # point, against the FP64 oracle's cold fit of the same frames
+    cold_or = oracle.process_batch(bt.frames, spec.bins, ref)
+    ok = cold_or["status"] == 0
+    fw = np.abs(cold_or["params"][ok, 1])
+    net_p0 = plan.mlp_infer(torch.from_numpy(ora["y"].astype(np.float32)).to(DEV)).cpu().numpy()
+    e_net = np.abs(net_p0[ok, 0] - cold_or["params"][ok, 0]) / fw
+    e_med = np.abs(cold_or["p0"][ok, 0] - cold_or["params"][ok, 0]) / fw
+    wc = np.abs(warm["params"].cpu().numpy()[ok, 0] - cold_or["params"][ok, 0]) / fw
+    _say(f"  start-point centre error vs cold fit, median FWHM: network {np.median(e_net):.4f}, "
+         f"7x7 median {np.median(e_med):.4f}; warm (2-iteration polish) within 1e-3 FWHM of the "
+         f"cold fit: {np.mean(wc <= 1e-3):.4f}")
+    assert np.median(e_net) < 0.5 * np.median(e_med)
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not built")
@@ -184,3 +253,12 @@ def test_warm_path_polish_to_convergence():
          f" parity {res['fraction']:.5f}, iters {warm['iters'].float().mean().item():.2f}")
     assert res["fraction"] >= PASS_FRACTION, res
     assert np.mean(st == ora["status"]) >= 0.99
+    # on frames that keep the network's start point, a full LM from it needs
+    # fewer iterations than the cold start from the 7x7 median
+    cold = plan.process(fr, want=("iters", "status"))
+    torch.cuda.synchronize()
+    keep = (st != 3) & (cold["status"].cpu().numpy() == 0)
+    wi = warm["iters"].cpu().numpy()[keep].mean()
+    ci = cold["iters"].cpu().numpy()[keep].mean()
+    _say(f"  iterations on {keep.sum()} frames: from the network {wi:.2f}, from the median {ci:.2f}")
+    assert wi < ci

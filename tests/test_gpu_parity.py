@@ -315,8 +315,10 @@ def test_end_to_end_shapes(n, k, nf):
 
 def test_paper_rate_full_batch_sampled():
     """65536 frames x 2048 samples, 220 teeth, in the launch configuration the
-    benchmark times; 64 sampled frames are recomputed by the oracle from their
-    7-frame neighbourhoods (all the 7x7 median needs)."""
+    benchmark times (three HIP streams are the benchmark's; one batch is one
+    launch sequence).  The oracle transforms and normalises the whole batch,
+    takes the 7x7-median start points over it, and fits 4096 randomly sampled
+    frames plus the batch edges; the bar is the plain path's 99.9 %."""
     _say("paper-rate full batch, sampled")
     spec = synth.spec_paper_rate()
     nf = 65536
@@ -326,33 +328,26 @@ def test_paper_rate_full_batch_sampled():
     fr = torch.from_numpy(bt.frames).to(DEV)
     params = torch.empty((nf, 4), dtype=torch.float32, device=DEV)
     plan.process_batch(fr, params)
-    out = plan.process(fr, want=("params", "teeth", "status"))
+    out = plan.process(fr, want=("params", "teeth", "status", "iters"))
     torch.cuda.synchronize()
     p_plain = params.cpu().numpy()
     g = {k: v.cpu().numpy() for k, v in out.items()}
     assert np.array_equal(p_plain, g["params"])         # deterministic, both entry points
+    mags = oracle.tooth_magnitudes(bt.frames, spec.bins)
+    assert mag_rel_err(g["teeth"], mags).max() <= MAG_RTOL
+    y = oracle.normalize(mags, ref)
+    p0 = oracle.initial_guess(y)
     rng = np.random.default_rng(5)
-    sample = np.sort(np.concatenate([[0, 1, nf - 1], rng.choice(np.arange(3, nf - 3), 61,
-                                                                 replace=False)]))
-    p_or, p_gpu, st_or, c2_or, y_or = [], [], [], [], []
-    for f in sample:
-        lo, hi = max(0, f - 3), min(nf, f + 4)
-        m = oracle.tooth_magnitudes(bt.frames[lo:hi], spec.bins)
-        assert mag_rel_err(g["teeth"][lo:hi], m).max() <= MAG_RTOL
-        y = oracle.normalize(m, ref)
-        # the batch edges replicate inside the batch, exactly as the oracle's pad does
-        p0 = oracle.initial_guess(y)[f - lo]
-        pr, it, st, c2 = oracle.lm_fit(y[f - lo], p0)
-        p_or.append(pr)
-        st_or.append(st)
-        c2_or.append(c2)
-        y_or.append(y[f - lo])
-        p_gpu.append(g["params"][f])
-    res = centre_parity(np.array(y_or), np.array(p_gpu), np.array(p_or), np.array(st_or),
-                        np.array(c2_or))
-    _say(f"  fraction={res['fraction']:.5f} exempt={res['exempt']} max_err={res['max_err']:.2e}")
-    assert res["fraction"] >= 0.98, res   # 64 samples: at most one miss
-    assert np.mean(g["status"] == 0) >= 0.98
+    sample = np.sort(np.concatenate([[0, 1, 2, nf - 3, nf - 2, nf - 1],
+                                     rng.choice(np.arange(3, nf - 3), 4096, replace=False)]))
+    p_or, it_or, st_or, c2_or = oracle.lm_fit_batch(y[sample], p0[sample])
+    res = centre_parity(y[sample], g["params"][sample], p_or, st_or, c2_or)
+    _say(f"  fraction={res['fraction']:.5f} of {res['n']} exempt={res['exempt']} "
+         f"max_err={res['max_err']:.2e}; iterations gpu {g['iters'][sample].mean():.2f} "
+         f"oracle {it_or.mean():.2f}")
+    assert res["fraction"] >= PASS_FRACTION, res
+    assert abs(g["iters"][sample].mean() - it_or.mean()) < 0.5
+    assert np.mean(g["status"] == 0) >= 0.999
 
 
 def test_empty_and_errors():

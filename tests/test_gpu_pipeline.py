@@ -1,9 +1,14 @@
 """Multi-stream ring pipeline on the GPU: per-slot captured graphs, interleaved
 bursts of streams with different frame lengths, tooth counts and fit forms.
-Every burst's results must equal what cg_process_batch_ex returns for the same
-frames (same kernels, so bit-identical), in publish order per stream; the
-autotuner must return one of its candidates."""
+* Every burst's results equal what cg_process_batch_ex returns for the same
+  frames (same kernels, so bit-identical), in publish order per stream.
+* The sixteen-stream configuration with the trained warm start matches the
+  FP64 oracle's warm path on a 1-in-16 sample of every burst at the plain
+  path's centre bar (>= 99.9 % within 1e-3 FWHM).
+* The autotuner installs one of its candidate shapes, and results stay at
+  the bar whatever shape it picks."""
 
+import os
 import sys
 
 import numpy as np
@@ -18,9 +23,12 @@ if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_2307_12988_amd as cg  # noqa: E402
+from oracle.pipeline import network_start, warm_fit  # noqa: E402
 from paper_2307_12988_amd import train_mlp  # noqa: E402
+from parity_util import PASS_FRACTION, centre_parity  # noqa: E402
 
 DEV = torch.device("cuda:0")
+WEIGHTS = os.path.join(os.path.dirname(cg.__file__), "data", "warmstart_learned.npz")
 
 
 def _say(m):
@@ -75,6 +83,69 @@ def test_pipeline_matches_process_batch():
     pipe.close()
 
 
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not built")
+def test_sixteen_streams_match_oracle():
+    d = np.load(WEIGHTS)
+    specs = synth.spec_multistream(seed=100)
+    assert len(specs) == 16
+    plans, data, noise = [], [], []
+    for s, sp in enumerate(specs):
+        bt = synth.make_batch(sp, 2048, seed=100 + s)
+        ref = oracle.reference_spectrum(bt.ref_frames, sp.bins).astype(np.float32)
+        # the stream's noise floor: median RMS residual of converged cold fits
+        cal = oracle.process_batch(bt.frames[:160], sp.bins, ref)
+        ok = cal["status"] == 0
+        nf_s = float(np.median(np.sqrt(cal["chi2"][ok] / (sp.k - 4))))
+        pl = cg.Plan(sp.n, sp.fs, sp.bins, ref)
+        pl.set_mlp(d["params"], d["out_mean"], d["out_std"], nf_s)
+        plans.append(pl)
+        data.append((bt.frames, ref))
+        noise.append(nf_s)
+    _say("sixteen streams: plans ready")
+    pipe = cg.Pipeline(plans, [cg.FIT_WARM_MLP] * 16, slots_per_stream=3, max_burst_frames=1024,
+                       keep_results=True)
+    rng = np.random.default_rng(11)
+    pos = [0] * 16
+    sent = {s: [] for s in range(16)}
+    seq = [0] * 16
+    for rnd in range(2):
+        for s in rng.permutation(16):
+            s = int(s)
+            n = int(rng.integers(256, 1025))
+            fr = np.ascontiguousarray(data[s][0][pos[s]:pos[s] + n])
+            pipe.put(s, torch.from_numpy(fr).to(DEV), seq[s])
+            sent[s].append((seq[s], fr))
+            pos[s] += n
+            seq[s] += 1
+    pipe.drain(120000)
+    st = pipe.stats()
+    _say(f"  stats {st}")
+    assert st["bursts"] == 32 and st["overflows"] == 0
+    assert st["dev_span_p50_ms"] > 0 and st["dev_lat_p50_ms"] > 0
+    ys, pg, po, so, co = [], [], [], [], []
+    for s, sp in enumerate(specs):
+        for want_seq, fr in sent[s]:
+            got = pipe.read(s)
+            assert got is not None and got[0] == want_seq
+            y = oracle.normalize(oracle.tooth_magnitudes(fr, sp.bins), data[s][1])
+            rows = np.arange(int(rng.integers(0, 16)), fr.shape[0], 16)
+            p0 = network_start(y[rows], d["params"].astype(np.float64), d["out_mean"],
+                               d["out_std"])
+            par, _, stat, c2, _ = warm_fit(y, p0, noise[s], rows=rows)
+            ys.append(y[rows])
+            pg.append(got[1][rows])
+            po.append(par)
+            so.append(np.where(stat == 3, 0, stat))
+            co.append(c2)
+        assert pipe.read(s) is None
+    pipe.close()
+    res = centre_parity(np.vstack(ys), np.vstack(pg), np.vstack(po), np.concatenate(so),
+                        np.concatenate(co))
+    _say(f"  oracle parity on {res['n']} sampled frames: {res['fraction']:.5f}, exempt "
+         f"{res['exempt']}, max {res['max_err']:.2e} FWHM")
+    assert res["fraction"] >= PASS_FRACTION, res
+
+
 def test_autotune_picks_a_candidate():
     sp = synth.spec_paper_rate()
     bt = synth.make_batch(sp, 8192, seed=1)
@@ -83,7 +154,21 @@ def test_autotune_picks_a_candidate():
     fr = torch.from_numpy(bt.frames).to(DEV)
     base = pl.process(fr, want=("params",))["params"].cpu().numpy()
     chunk, ms = pl.autotune(fr)
-    _say(f"autotune: chunk {chunk}, {ms:.3f} ms")
-    assert chunk in (4, 8, 16, 32, 64) and ms > 0
+    shape = pl.tuned_shape()
+    _say(f"autotune: {shape}, {ms:.3f} ms")
+    assert shape["lm_lanes"] in (8, 16) and chunk == shape["lm_chunk"] and ms > 0
+    assert chunk in (8, 16, 32, 64) if shape["lm_lanes"] == 8 else chunk in (4, 8, 16, 32)
     again = pl.process(fr, want=("params",))["params"].cpu().numpy()
-    assert np.array_equal(base, again)
+    if shape["lm_lanes"] == 8:
+        # the default shape for 220 teeth: only the order of work changed
+        assert np.array_equal(base, again)
+    # whatever the shape, the centres stay at the bar against the oracle
+    sample = np.arange(3, 8189, 8)
+    y = oracle.normalize(oracle.tooth_magnitudes(bt.frames, sp.bins), ref)
+    p0 = oracle.initial_guess(y)
+    p_or, _, st_or, c2_or = oracle.lm_fit_batch(y[sample], p0[sample])
+    res = centre_parity(y[sample], again[sample], p_or, st_or, c2_or)
+    assert res["fraction"] >= PASS_FRACTION, res
+    for knob, bad in ((cg.TUNE_LM_LANES, 4), (cg.TUNE_LM_LANES, 32), (cg.TUNE_FFT_BLOCKS, -1)):
+        with pytest.raises(cg.CombGpuError):
+            pl.set_tuning(knob, bad)

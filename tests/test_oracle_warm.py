@@ -126,3 +126,17 @@ def test_polish_from_exact_start_on_noiseless_spectra():
     params, iters, status, chi2, fell = warm_fit(y, np.array(truths), 1e-3)
     assert not fell.any() and np.all(status == 0) and np.all(iters <= 1)
     assert np.allclose(params, truths, rtol=0, atol=1e-9)
+
+
+def test_row_sampled_warm_fit_equals_full_batch_rows():
+    k = 100
+    rng = np.random.default_rng(3)
+    truths = [(20.0 + 3 * i, 8.0, 0.6, 1.0) for i in range(12)]
+    y = np.vstack([_dip(k, *t) for t in truths]) + 0.01 * rng.standard_normal((12, k))
+    p0 = np.array(truths) + [0.3, 0.5, 0.02, 0.0]
+    full = warm_fit(y, p0, 0.005)
+    rows = np.array([0, 1, 5, 6, 9])
+    part = warm_fit(y, p0[rows], 0.005, rows=rows)
+    for a, b in zip(full, part):
+        assert np.array_equal(a[rows], b)
+    assert full[4].any() and not full[4].all()      # both branches exercised
