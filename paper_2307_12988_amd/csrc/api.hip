@@ -157,6 +157,7 @@ const char* cg_version(void) { return "combgpu-mi355x 0.1.0 gfx950"; }
 
 cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins,
                          int32_t n_teeth, const float* ref_spectrum, cg_plan** out_plan) {
+  cg::set_detail("");
   if (!out_plan) return CG_ERR_NULL;
   *out_plan = nullptr;
   cg_status st = cg::check_geometry(frame_len, fs, tooth_bins, n_teeth);
@@ -241,6 +242,7 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
                               int32_t* out_iters, int32_t* out_status, float* out_chi2,
                               float* out_teeth, float* out_y, uint32_t flags, void* workspace,
                               size_t workspace_bytes, void* stream) {
+  cg::set_detail("");
   if (!p) return CG_ERR_NULL;
   if (nf < 0) return CG_ERR_INVALID_ARG;
   if ((flags & ~(CG_DFT_MASK | CG_FIT_MASK)) != 0u) return CG_ERR_INVALID_ARG;

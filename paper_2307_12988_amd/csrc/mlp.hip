@@ -374,12 +374,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     if (k == MLP_IN) {
       walk([&](int64_t f, int j) { return y[f * k + j]; });
     } else {
+      // position j (k - 1) / 219 split exactly into its integer part and
+      // remainder, so the interpolation weight carries one rounding only
       walk([&](int64_t f, int j) {
-        const float pos = (float)j * (float)(k - 1) / (float)(MLP_IN - 1);
-        int lo = (int)floorf(pos);
-        lo = lo < 0 ? 0 : (lo > k - 1 ? k - 1 : lo);
+        const int q = j * (k - 1);
+        int lo = q / (MLP_IN - 1);
+        const float t = (float)(q - lo * (MLP_IN - 1)) / (float)(MLP_IN - 1);
+        lo = lo > k - 1 ? k - 1 : lo;
         const int hi = lo + 1 < k ? lo + 1 : k - 1;
-        const float t = pos - (float)lo;
         return y[f * k + lo] * (1.f - t) + y[f * k + hi] * t;
       });
     }

@@ -30,6 +30,15 @@ def mag_rel_err(gpu, ora):
     return np.abs(gpu - ora) / np.maximum(np.abs(ora), 1e-300)
 
 
+def warm_compared(status):
+    """Statuses for centre_parity on the warm path: both sides run the same
+    short polish, so a frame is compared whether the polish converged (0),
+    stopped at its iteration cap (1) or fell back to the cold fit (3); only a
+    singular fit (2) is left out."""
+    st = np.asarray(status)
+    return np.where(st == 2, 2, 0)
+
+
 def centre_parity(y_oracle, p_gpu, p_oracle, st_oracle, chi2_oracle):
     """Returns dict with fraction passing, exemptions and the outlier rows."""
     p_gpu = np.asarray(p_gpu, dtype=np.float64)

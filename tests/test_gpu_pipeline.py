@@ -25,7 +25,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 import paper_2307_12988_amd as cg  # noqa: E402
 from oracle.pipeline import network_start, warm_fit  # noqa: E402
 from paper_2307_12988_amd import train_mlp  # noqa: E402
-from parity_util import PASS_FRACTION, centre_parity  # noqa: E402
+from parity_util import PASS_FRACTION, centre_parity, warm_compared  # noqa: E402
 
 DEV = torch.device("cuda:0")
 WEIGHTS = os.path.join(os.path.dirname(cg.__file__), "data", "warmstart_learned.npz")
@@ -122,7 +122,8 @@ def test_sixteen_streams_match_oracle():
     _say(f"  stats {st}")
     assert st["bursts"] == 32 and st["overflows"] == 0
     assert st["dev_span_p50_ms"] > 0 and st["dev_lat_p50_ms"] > 0
-    ys, pg, po, so, co = [], [], [], [], []
+    n_tot = good = exempt = 0
+    worst = 0.0
     for s, sp in enumerate(specs):
         for want_seq, fr in sent[s]:
             got = pipe.read(s)
@@ -132,18 +133,17 @@ def test_sixteen_streams_match_oracle():
             p0 = network_start(y[rows], d["params"].astype(np.float64), d["out_mean"],
                                d["out_std"])
             par, _, stat, c2, _ = warm_fit(y, p0, noise[s], rows=rows)
-            ys.append(y[rows])
-            pg.append(got[1][rows])
-            po.append(par)
-            so.append(np.where(stat == 3, 0, stat))
-            co.append(c2)
+            res = centre_parity(y[rows], got[1][rows], par, warm_compared(stat), c2)
+            n_tot += res["n"]
+            good += round(res["fraction"] * res["n"])
+            exempt += res["exempt"]
+            worst = max(worst, res["max_err"])
         assert pipe.read(s) is None
     pipe.close()
-    res = centre_parity(np.vstack(ys), np.vstack(pg), np.vstack(po), np.concatenate(so),
-                        np.concatenate(co))
-    _say(f"  oracle parity on {res['n']} sampled frames: {res['fraction']:.5f}, exempt "
-         f"{res['exempt']}, max {res['max_err']:.2e} FWHM")
-    assert res["fraction"] >= PASS_FRACTION, res
+    frac = good / max(n_tot, 1)
+    _say(f"  oracle parity on {n_tot} sampled frames: {frac:.5f}, exempt {exempt}, "
+         f"max {worst:.2e} FWHM")
+    assert n_tot > 1000 and frac >= PASS_FRACTION
 
 
 def test_autotune_picks_a_candidate():
