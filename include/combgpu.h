@@ -158,6 +158,33 @@ cg_status cg_process_batch_ex(cg_plan* plan, const int16_t* frames, int64_t n_fr
                               void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the whole
+ * path of cg_process_batch_ex with its workspace (normalised spectra, start
+ * points, chi2, fallback flags, list and count) in a fixed device array that
+ * the library carries, CG_STATIC_SCRATCH_BYTES bytes on each GPU it runs on,
+ * held until the process ends.  The call allocates nothing: no hipMalloc, no
+ * hipFree, no allocating library routine.
+ *   frames, out_params, out_iters, out_status, out_chi2, flags, stream as for
+ *   cg_process_batch_ex (out_teeth / out_y are not offered); flags must name
+ *   the FFT form (CG_DFT_FFT) with CG_FIT_COLD or CG_FIT_WARM_MLP (the
+ *   matrix-core forms build a basis on first use, which allocates).
+ * Needs cg_workspace_bytes(plan, n_frames) <= CG_STATIC_SCRATCH_BYTES (for
+ * 220 teeth: up to 72 000 frames); larger batches get CG_ERR_WORKSPACE and
+ * nothing is enqueued.  The array's address on a device is resolved when a
+ * plan is created there.
+ * Every call on one GPU shares that GPU's array, which keeps the contents of
+ * the last call; nothing in it needs to start at zero (the fallback count is
+ * cleared by the kernels).  Calls that overlap on one GPU (on different
+ * streams, or from different threads) race on the array: the caller orders
+ * them.
+ */
+#define CG_STATIC_SCRATCH_BYTES (64u << 20)
+cg_status cg_process_batch_static(cg_plan* plan, const int16_t* frames, int64_t n_frames,
+                                  float* out_params, int32_t* out_iters, int32_t* out_status,
+                                  float* out_chi2, uint32_t flags, void* stream);
+
+/*
  * Transform stage only: amplitudes at the tooth bins and/or normalised
  * spectra (either output may be NULL, not both).  `flags` selects the DFT form
  * (CG_DFT_*).  frames device int16[n_frames][frame_len]; outputs device

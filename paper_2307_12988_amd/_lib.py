@@ -34,6 +34,7 @@ SIGNATURES = {
     "cg_process_batch": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_process_batch_ex": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _vp, _sz,
                                    _vp]),
+    "cg_process_batch_static": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _u32, _vp]),
     "cg_teeth": (_i32, [_vp, _vp, _i64, _vp, _vp, _u32, _vp]),
     "cg_reference_from_frames": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_init_spectra": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),

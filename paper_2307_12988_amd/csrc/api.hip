@@ -201,6 +201,7 @@ cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins
   CG_TRY(cg::upload_reference(p, ref_spectrum), "copy ref");
   CG_TRY(hipMemcpy(p->d_tw, tw.data(), sizeof(float2) * frame_len, hipMemcpyHostToDevice),
          "copy twiddles");
+  CG_TRY(cg::resolve_static_scratch(p->device), "fixed scratch: hipGetSymbolAddress");
 #undef CG_TRY
   p->fft_blocks = cg::fft_grid_limit(p);
   *out_plan = p;
@@ -238,11 +239,20 @@ cg_status cg_workspace_bytes(const cg_plan* p, int64_t n_frames, size_t* bytes) 
   return CG_OK;
 }
 
-cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, float* out_params,
-                              int32_t* out_iters, int32_t* out_status, float* out_chi2,
-                              float* out_teeth, float* out_y, uint32_t flags, void* workspace,
-                              size_t workspace_bytes, void* stream) {
-  cg::set_detail("");
+}  // extern "C"
+
+namespace cg {
+namespace {
+
+// The whole path of cg_process_batch_ex.  Workspace: the caller's buffer if
+// given, else the fixed scratch array when no_alloc (no allocation of any
+// kind, matrix-core forms refused since they build their basis on first use),
+// else the plan's own, grown on demand.
+cg_status process_impl(cg_plan* p, const int16_t* frames, int64_t nf, float* out_params,
+                       int32_t* out_iters, int32_t* out_status, float* out_chi2,
+                       float* out_teeth, float* out_y, uint32_t flags, void* workspace,
+                       size_t workspace_bytes, void* stream, bool no_alloc) {
+  set_detail("");
   if (!p) return CG_ERR_NULL;
   if (nf < 0) return CG_ERR_INVALID_ARG;
   if ((flags & ~(CG_DFT_MASK | CG_FIT_MASK)) != 0u) return CG_ERR_INVALID_ARG;
@@ -260,6 +270,10 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
     return CG_ERR_INVALID_ARG;
   }
   if (dft != CG_DFT_FFT) {
+    if (no_alloc) {
+      cg::set_detail("the entry point that allocates nothing supports the FFT form only");
+      return CG_ERR_INVALID_ARG;
+    }
     if (!cg::aligned(frames, 16)) {
       cg::set_detail("matrix-core DFT forms need 16-byte aligned frames");
       return CG_ERR_INVALID_ARG;
@@ -282,6 +296,18 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
       return CG_ERR_INVALID_ARG;
     }
     ws = static_cast<char*>(workspace);
+  } else if (no_alloc) {
+    if (need > (size_t)CG_STATIC_SCRATCH_BYTES) {
+      cg::set_detail("batch needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                     std::to_string((size_t)CG_STATIC_SCRATCH_BYTES) +
+                     " bytes of the fixed scratch array");
+      return CG_ERR_WORKSPACE;
+    }
+    ws = static_cast<char*>(cg::static_scratch(p->device));
+    if (!ws) {
+      cg::set_detail("fixed scratch array not resolved on the plan's device");
+      return CG_ERR_STATE;
+    }
   } else {
     cg_status st = cg::ensure_ws(p, need);
     if (st != CG_OK) return st;
@@ -324,6 +350,26 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
                     p->lm_chunk, nullptr, nullptr, p->lm_lanes);
   if (e != hipSuccess) return hip_fail(e, "lm launch");
   return CG_OK;
+}
+
+}  // namespace
+}  // namespace cg
+
+extern "C" {
+
+cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, float* out_params,
+                              int32_t* out_iters, int32_t* out_status, float* out_chi2,
+                              float* out_teeth, float* out_y, uint32_t flags, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  return cg::process_impl(p, frames, nf, out_params, out_iters, out_status, out_chi2, out_teeth,
+                          out_y, flags, workspace, workspace_bytes, stream, false);
+}
+
+cg_status cg_process_batch_static(cg_plan* p, const int16_t* frames, int64_t nf,
+                                  float* out_params, int32_t* out_iters, int32_t* out_status,
+                                  float* out_chi2, uint32_t flags, void* stream) {
+  return cg::process_impl(p, frames, nf, out_params, out_iters, out_status, out_chi2, nullptr,
+                          nullptr, flags, nullptr, 0, stream, true);
 }
 
 cg_status cg_process_batch(cg_plan* p, const int16_t* frames, int64_t nf, float* out_params,

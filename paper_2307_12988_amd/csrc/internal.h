@@ -46,6 +46,11 @@ constexpr int kWaveSize = 64;
 // Copy a reference spectrum (host, k values) and its 0.5/ref table to the plan.
 hipError_t upload_reference(cg_plan* p, const float* ref);
 
+// Device address of the fixed scratch array on `device` (resolved once per
+// device by resolve_static_scratch, called at plan creation; null before).
+hipError_t resolve_static_scratch(int device);
+void* static_scratch(int device);
+
 // Record a HIP failure as the thread's error detail and map it to a status.
 cg_status hip_fail(hipError_t e, const char* where);
 void set_detail(const std::string& s);

@@ -161,6 +161,23 @@ class Plan:
         _lib.check(st, "cg_process_batch_ex")
         return out
 
+    def process_static(self, frames, params=None, iters=None, status=None, chi2=None,
+                       flags: int = 0):
+        """Whole path with the library's fixed scratch array as workspace
+        (cg_process_batch_static: no device allocation inside the call).
+        Outputs not passed are allocated here, before the call."""
+        nf, fp = self._frames(frames)
+        dev = frames.device
+        if params is None:
+            params = torch.empty((nf, 4), dtype=torch.float32, device=dev)
+        st = self._lib.cg_process_batch_static(
+            self._h, fp, nf, _dev_ptr(params, torch.float32, (nf, 4), "params"),
+            _dev_ptr(iters, torch.int32, (nf,), "iters"),
+            _dev_ptr(status, torch.int32, (nf,), "status"),
+            _dev_ptr(chi2, torch.float32, (nf,), "chi2"), int(flags), _stream(dev))
+        _lib.check(st, "cg_process_batch_static")
+        return params
+
     def process_batch(self, frames, params):
         """Plain entry point: writes params [n, 4] (centre, width, depth, baseline)."""
         nf, fp = self._frames(frames)
