@@ -358,7 +358,7 @@ cg_status cg_get_tuning(const cg_plan* plan, int32_t knob, int32_t* value);
  * Latency from publish to results is recorded on the host clock (until the
  * dispatcher sees the burst complete) and on the GPU's wall clock (until the
  * results are in host memory; the publish time is mapped onto the GPU clock
- * by the smallest launch-to-start gap seen in the last second or two).  Plans
+ * by the smallest launch-to-start gap seen in the last 0.1-0.2 s).  Plans
  * must outlive the pipeline and must not change while it exists.
  *
  * options: CG_PIPE_KEEP_RESULTS keeps each completed burst's results (and its

@@ -33,11 +33,12 @@
 // * Latency: the graph stamps the GPU's constant-rate wall clock when it
 //   starts and after the results are written.  The host clock and the GPU
 //   clock are tied by the smallest (graph start - launch call) seen in the
-//   last second or two (a launch cannot start before it is issued, and the
-//   quickest launches start within microseconds), which maps the publish
-//   time onto the GPU clock: publish -> results written is then read off
-//   the GPU's own clock.  The host-clock publish -> completion-seen latency
-//   is kept beside it.
+//   last 0.1-0.2 s (a launch cannot start before it is issued, and when the
+//   GPU has spare queues the quickest launches start within microseconds),
+//   which maps the publish time onto the GPU clock: publish -> results
+//   written is then read off the GPU's own clock.  Under a full load the
+//   quickest start may itself wait, which biases this figure low; the
+//   host-clock publish -> completion-seen latency is kept beside it.
 // * Dry run (CG_PIPE_DRY_RUN): the same bookkeeping with no device work; a
 //   burst "completes" after dry_us_per_frame * n microseconds.  Used to test
 //   overflow handling and ordering on machines without a GPU.
@@ -137,7 +138,8 @@ struct cg_pipeline {
   std::vector<float> dev_span_ms; // GPU clock: graph start -> results written
   double clk_hz = 1e8;            // GPU wall-clock rate
   // host time = GPU clock / clk_hz - offset; offset estimated by the
-  // smallest launch-to-start gap, over the current and the previous second
+  // smallest launch-to-start gap over the current and the previous 0.1 s
+  // (short windows, so that a drift between the two clocks does not bias it)
   double off_cur = 1e300, off_prev = 1e300, off_epoch = 0.0;
 };
 
@@ -322,7 +324,7 @@ void complete(cg_pipeline* P, const Burst& q, double t) {
     const double g0 = (double)sl.h_ts[0] / P->clk_hz, g1 = (double)sl.h_ts[1] / P->clk_hz;
     // GPU clock minus host clock, bounded below by the launch-to-start gap
     const double gap = g0 - sl.t_launch;
-    if (t - P->off_epoch > 1.0) {
+    if (t - P->off_epoch > 0.1) {
       P->off_prev = P->off_cur;
       P->off_cur = 1e300;
       P->off_epoch = t;
