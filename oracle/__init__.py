@@ -13,6 +13,7 @@ dft          ingest cast, DFT at the comb-tooth bins, magnitude, reference avera
 normalize    division by the reference spectrum
 initializer  7x7 median filter over the (frame, tooth) image and the start point
 lm           Levenberg-Marquardt fit of the Lorentzian cavity dip
+fano         projected Levenberg-Marquardt fit of the asymmetric Fano dip
 mlp          FP64 forward/backward of the warm-start network
 pipeline     the steps above chained for a batch of frames
 
@@ -24,7 +25,8 @@ from .dft import frames_to_float, dft_at_bins, tooth_magnitudes, reference_spect
 from .normalize import normalize
 from .initializer import median7x7, initial_guess
 from .lm import lorentzian, lorentzian_jacobian, lm_fit, lm_fit_batch, chi2_at
-from .pipeline import process_batch
+from .pipeline import process_batch, process_batch_fano
+from .fano import fano, fano_jacobian, fano_fit, fano_fit_batch, fano_box, chi2_fano
 
 __all__ = [
     "frames_to_float",
@@ -41,4 +43,11 @@ __all__ = [
     "lm_fit_batch",
     "chi2_at",
     "process_batch",
+    "process_batch_fano",
+    "fano",
+    "fano_jacobian",
+    "fano_fit",
+    "fano_fit_batch",
+    "fano_box",
+    "chi2_fano",
 ]

@@ -28,6 +28,22 @@ def process_batch(frames, bins, ref, max_iter: int = 20, tol: float = 1e-6):
             "status": status, "chi2": chi2}
 
 
+def process_batch_fano(frames, bins, ref, width, q, dbar, bbar, max_iter: int = 20,
+                       tol: float = 1e-6, rows=None):
+    """The paper's own fit for a batch: transform, teeth, reference division,
+    7x7-median start centres, and the box-constrained LM fit of the Fano dip
+    with width and asymmetry fixed and extent and scale within +-10 % of the
+    averages dbar, bbar (every frame, or `rows`)."""
+    from .fano import fano_box, fano_fit_batch
+    mags = tooth_magnitudes(frames, bins)
+    y = normalize(mags, ref)
+    p0 = initial_guess(y)
+    params, iters, status, chi2 = fano_fit_batch(y, p0[:, 0], width, q, dbar, bbar, max_iter,
+                                                 tol, rows)
+    return {"mags": mags, "y": y, "p0": p0, "box": fano_box(dbar, bbar), "params": params,
+            "iters": iters, "status": status, "chi2": chi2}
+
+
 def network_start(y, params, out_mean, out_std):
     """Start points of the learned warm start for spectra y [F, K]: the
     network's standardised outputs z mapped to p = z * std + mean, computed on

@@ -19,6 +19,7 @@ from .comb import (
     spec_precision,
     spec_learned,
     spec_multistream,
+    spec_fano,
 )
 
 __all__ = [
@@ -33,4 +34,5 @@ __all__ = [
     "spec_precision",
     "spec_learned",
     "spec_multistream",
+    "spec_fano",
 ]

@@ -88,6 +88,10 @@ class StreamSpec:
     tilt: Tuple[float, float] = (0.0, 0.0)
     bits: int = 14
     headroom: float = 0.8
+    lineshape: str = "lorentzian"      # "lorentzian" or "fano"
+    asym_q: float = float("inf")       # Fano asymmetry (fano lineshape only)
+    power_drift: float = 0.0           # laser-power drift of the baseline, +- fraction
+    power_drift_hz: float = 1700.0
 
     @property
     def k(self) -> int:
@@ -192,6 +196,10 @@ def make_batch(spec: StreamSpec, n_frames: int, seed: int, batch_index: int = 0,
     else:
         raise ValueError(spec.centre_mode)
     baseline = np.full(n_frames, float(spec.baseline))
+    if spec.power_drift:
+        phase = rng.uniform(0.0, 2.0 * np.pi)
+        baseline = baseline * (1.0 + spec.power_drift
+                               * np.sin(2.0 * np.pi * spec.power_drift_hz * t_start + phase))
 
     gain = stream_gain(spec)
     phases = _phases(k)
@@ -202,7 +210,11 @@ def make_batch(spec: StreamSpec, n_frames: int, seed: int, batch_index: int = 0,
     for a in range(0, n_frames, chunk):
         b = min(n_frames, a + chunk)
         u = 2.0 * (i[None, :] - centre[a:b, None]) / width[a:b, None]
-        amps = baseline[a:b, None] * (1.0 - depth[a:b, None] / (1.0 + u * u))
+        if spec.lineshape == "fano":
+            shape = (1.0 + u / spec.asym_q) ** 2 / (1.0 + u * u)
+        else:
+            shape = 1.0 / (1.0 + u * u)
+        amps = baseline[a:b, None] * (1.0 - depth[a:b, None] * shape)
         amps = amps * (1.0 + tilt[a:b, None] * (i[None, :] - half) / half)
         s = _synth(n, bins, amps, phases)
         if noise:
@@ -270,6 +282,18 @@ def spec_learned() -> StreamSpec:
     return StreamSpec(name="learned", n=2048, fs=1.1e9, bins=tooth_bins_interleaved(2048, 220),
                       centre_mode="drift", centre_halfrange=40.0, width=(3.0, 20.0),
                       depth=(0.1, 0.9), snr_db=(15.0, 50.0), tilt=(-0.05, 0.05))
+
+
+def spec_fano() -> StreamSpec:
+    """The paper's own lineshape at the paper rate: 2048-sample frames at
+    1.1 GS/s, 220 teeth, an asymmetric Fano dip of fixed width 8.03 teeth
+    (the cavity linewidth: free spectral range over finesse, in 10 MHz
+    teeth) and asymmetry q = 4, depth 0.6, the baseline following a +-5 %
+    laser-power drift at 1.7 kHz, centre +-10 teeth at 23.686 kHz, SNR
+    U[20,50] dB."""
+    return StreamSpec(name="fano", n=2048, fs=1.1e9, bins=tooth_bins_interleaved(2048, 220),
+                      width=(8.03, 8.03), depth=(0.6, 0.6), snr_db=(20.0, 50.0),
+                      lineshape="fano", asym_q=4.0, power_drift=0.05)
 
 
 def spec_multistream(seed: int = 100, n_streams: int = 16) -> Sequence[StreamSpec]:
