@@ -372,6 +372,285 @@ def warm_forms(args, torch, cg, dev):
     plan.close()
 
 
+FANO_W, FANO_Q, FANO_DBAR, FANO_BBAR = 8.03, 4.0, 0.6, 1.0
+
+
+def fano_flops(k, iters):
+    """Algorithmic work of the Fano fit by the FP32-vector count: about 50 K
+    flops per iteration for the model, the three Jacobian columns and the
+    nine normal-equation sums over K teeth, plus about 60 for the damped 3x3
+    solve."""
+    return float(np.sum(np.asarray(iters, dtype=np.float64))) * (50.0 * k + 60.0)
+
+
+def fano_workload(args, torch, cg, dev):
+    """The paper's own fit at the paper rate: batches of 65536 frames x 2048
+    int16 samples of the Fano stream (fixed width 8.03 teeth, asymmetry 4,
+    depth 0.6, +-5 % laser-power drift), FFT, tooth gather, normalisation,
+    7x7-median start centre and the boxed Fano LM (extent and scale within
+    +-10 % of 0.6 and 1.0).  Same timing scheme as the headline workload."""
+    spec = synth.spec_fano()
+    nf, n, k = args.frames, spec.n, spec.k
+    _log(f"generating {args.pool} batches of {nf} x {n} int16 (Fano stream) ...")
+    pool_np, ref_np = make_pool(spec, nf, args.pool, workers=min(args.pool, 8))
+    first_np = pool_np[0]
+    pool = [torch.from_numpy(fr).to(dev) for fr in pool_np]
+    del pool_np
+    plan = cg.Plan(n, spec.fs, spec.bins, np.ones(k, dtype=np.float32))
+    ref = plan.reference_from_frames(torch.from_numpy(ref_np).to(dev)).cpu().numpy()
+    plan.set_reference(ref)
+    plan.set_fano(FANO_W, FANO_Q, FANO_DBAR, FANO_BBAR)
+    ns = max(1, args.streams)
+    streams = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(dev) for _ in range(ns - 1)]
+    wss = [torch.empty(plan.workspace_bytes(nf), dtype=torch.uint8, device=dev) for _ in range(ns)]
+    outs = [(torch.empty((nf, 4), dtype=torch.float32, device=dev),
+             torch.empty((nf,), dtype=torch.int32, device=dev),
+             torch.empty((nf,), dtype=torch.int32, device=dev)) for _ in range(ns)]
+
+    def step(i):
+        j = i % ns
+        with torch.cuda.stream(streams[j]):
+            plan.process(pool[i % len(pool)], params=outs[j][0], iters=outs[j][1],
+                         status=outs[j][2], workspace=wss[j], flags=cg.FIT_FANO, want=())
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    step(0)
+    torch.cuda.synchronize(dev)
+    params0 = outs[0][0].cpu().numpy()
+    it_np = outs[0][1].cpu().numpy()
+    st_np = outs[0][2].cpu().numpy()
+    # per-kernel durations with events on the launching stream
+    y = torch.empty((nf, k), dtype=torch.float32, device=dev)
+    p0 = torch.empty((nf, 4), dtype=torch.float32, device=dev)
+    fit_out = (torch.empty((nf, 4), dtype=torch.float32, device=dev),
+               torch.empty((nf,), dtype=torch.int32, device=dev),
+               torch.empty((nf,), dtype=torch.int32, device=dev),
+               torch.empty((nf,), dtype=torch.float32, device=dev))
+    stream = torch.cuda.current_stream(dev)
+    rot = [0]
+
+    def fft_launch():
+        rot[0] += 1
+        plan.teeth(pool[rot[0] % len(pool)], want_mag=False, want_y=True, out_y=y)
+
+    plan.teeth(pool[0], want_mag=False, want_y=True, out_y=y)
+    launch = {"fft_teeth": fft_launch,
+              "median_start": lambda: plan.init_spectra(y, out_p0=p0),
+              "fano_fit": lambda: plan.fit_fano(y, p0, out=fit_out)}
+    plan.init_spectra(y, out_p0=p0)
+    reps = max(3, min(args.steps, 10))
+    ms = {}
+    for nm, fn in launch.items():
+        fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize(dev)
+        ms[nm] = ev[0].elapsed_time(ev[1]) / reps
+    it_fit = fit_out[1].cpu().numpy()
+    fit_tf = fano_flops(k, it_fit) / (ms["fano_fit"] * 1e-3) / 1e12
+    fft_gbs = nf * (2 * n + 4 * k) / (ms["fft_teeth"] * 1e-3) / 1e9
+    dom = max(ms, key=ms.get)
+    if dom == "fano_fit":
+        roof = {"kernel": dom, "bound": "alu", "achieved": fit_tf, "peak": VALU_FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": fit_tf / VALU_FP32_PEAK_TFLOPS, "traffic": None,
+                "flop_count": "sum over frames of LM iterations x (50 K + 60)"}
+    elif dom == "fft_teeth":
+        roof = {"kernel": dom, "bound": "hbm", "achieved": fft_gbs, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": fft_gbs / HBM_PEAK_GBS, "traffic": None}
+    else:
+        ach = MEDIAN_OPS_PER_OUTPUT * nf * k / (ms[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": VALU_OPS_PEAK_TOPS,
+                "unit": "Top/s", "frac": ach / VALU_OPS_PEAK_TOPS, "traffic": None}
+    line = {"metric": METRIC, "value": nf * n * 2 * args.steps / wall / 1e9, "unit": "GB/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"paper's Fano fit: {nf} frames x {n} int16 samples per batch, "
+                                   f"{k} teeth, width {FANO_W} and asymmetry {FANO_Q} fixed, extent "
+                                   f"and scale boxed +-10% of {FANO_DBAR} and {FANO_BBAR}",
+                       "frames_per_batch": nf, "frame_len": n, "n_teeth": k,
+                       "pool_batches": args.pool, "streams": ns},
+            "spectra_per_s": nf * args.steps / wall,
+            "fit": {"mean_iters": float(it_np.mean()),
+                    "status_counts": np.bincount(st_np, minlength=3).tolist()},
+            "stages": {nm: {"ms": v} for nm, v in ms.items()},
+            "roofline": roof}
+    line["stages"]["fano_fit"]["achieved_TFLOPs"] = fit_tf
+    line["stages"]["fft_teeth"]["achieved_GBps"] = fft_gbs
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.pipeline import process_batch_fano
+        ns_cpu = min(args.cpu_frames, 16384, nf)
+        t0 = time.perf_counter()
+        ora = process_batch_fano(first_np[:ns_cpu], spec.bins, ref, FANO_W, FANO_Q, FANO_DBAR,
+                                 FANO_BBAR)
+        dt = time.perf_counter() - t0
+        m = ns_cpu - 3
+        conv = ora["status"][:m] == 0
+        err = np.abs(params0[:m, 0] - ora["params"][:m, 0]) / FANO_W
+        line["cpu_baseline"] = {"value": ns_cpu * n * 2 / dt / 1e9, "unit": "GB/s",
+                                "spectra_per_s": ns_cpu / dt, "cores": None, "kind": "oracle",
+                                "sample": f"first {ns_cpu} frames of batch 0 (FP64 oracle's "
+                                          f"whole Fano path), {dt:.1f} s",
+                                "host": host_info(),
+                                "parity_vs_gpu": {"frames": int(conv.sum()),
+                                                  "centre_within_1e-3_fwhm":
+                                                      float(np.mean(err[conv] <= 1e-3)),
+                                                  "max_err_fwhm": float(err[conv].max())}}
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
+def host_ingest(args, torch, cg, dev):
+    """The paper's data path, digitiser -> pinned host ring -> GPU: one
+    paper-rate stream (2048-sample int16 frames, 220 teeth, cold-start fit) in
+    bursts of 32768 frames (128 MiB) through the ring pipeline with a host
+    ring (each burst copied host -> device on a copy stream while earlier
+    bursts compute on two lanes, so bursts can complete out of order and are
+    re-sorted on read).  Phases: (A) maximum rate with the ring written in
+    place (a digitiser's DMA into the ring costs the host nothing), the
+    PCIe-inclusive consumption rate; (B) paced at 22 GB/s (ten times the
+    paper's 2.2 GB/s) the same way, overflows counted; (C) paced at the
+    paper's 2.2 GB/s with the host copying every burst into the ring.
+    Accuracy: a 1-in-64 sample of four bursts against the FP64 oracle."""
+    spec = synth.spec_paper_rate()
+    n, k = spec.n, spec.k
+    burst = 32768
+    n_pool = 8
+    slots, lanes = args.slots if args.slots != 8 else 6, 2
+    _log(f"generating {n_pool} host bursts of {burst} x {n} int16 ...")
+    pool_np, ref_np = make_pool(spec, burst, n_pool, workers=min(n_pool, 8))
+    plan = cg.Plan(n, spec.fs, spec.bins, np.ones(k, dtype=np.float32))
+    ref = plan.reference_from_frames(torch.from_numpy(ref_np).to(dev)).cpu().numpy()
+    plan.set_reference(ref)
+    bb = burst * n * 2
+
+    def fill_all(pipe, seq0):
+        for j in range(slots):
+            pipe.put(0, pool_np[j % n_pool], seq0 + j)
+        pipe.drain(120000)
+        return seq0 + slots
+
+    def run_in_place(pipe, seconds, rate_gbs, seq):
+        """Publish pre-filled slots (their contents are a previous burst),
+        paced to rate_gbs (0 = as fast as slots free up)."""
+        full = 0
+        t0 = time.perf_counter()
+        due = t0
+        while True:
+            now = time.perf_counter()
+            if now - t0 >= seconds:
+                break
+            if rate_gbs and now < due:
+                continue
+            try:
+                slot, _ = pipe.acquire(0)
+            except cg.RingFull:
+                full += 1
+                if rate_gbs:
+                    due += bb / (rate_gbs * 1e9)   # the burst is lost
+                continue
+            pipe.publish(0, slot, burst, seq)
+            seq += 1
+            due += bb / (rate_gbs * 1e9) if rate_gbs else 0.0
+        pipe.drain(120000)
+        return seq, full
+
+    out = {}
+    # (A) and (B): ring written in place
+    for name, secs, rate in (("A_max_rate_in_place", 10.0, 0.0),
+                             ("B_paced_22GBps_in_place", 20.0, 22.0)):
+        pipe = cg.Pipeline([plan], [cg.FIT_COLD], slots_per_stream=slots, max_burst_frames=burst,
+                           lanes=lanes, host_ring=True)
+        seq = fill_all(pipe, 0)
+        base = pipe.stats()
+        _log(f"phase {name} ...")
+        seq, full = run_in_place(pipe, secs, rate, seq)
+        st = pipe.stats()
+        pipe.close()
+        bursts = st["bursts"] - base["bursts"]
+        out[name] = {"seconds": secs, "bursts": bursts, "GBps": bursts * bb / secs / 1e9,
+                     "ring_full_events": full, "overflows": st["overflows"] - base["overflows"],
+                     "out_of_order": st["out_of_order"], "lat_p50_ms": st["lat_p50_ms"],
+                     "lat_p99_ms": st["lat_p99_ms"], "dev_lat_p50_ms": st["dev_lat_p50_ms"],
+                     "dev_lat_p99_ms": st["dev_lat_p99_ms"]}
+    # (C): the paper's rate, the host writing every burst into the ring
+    pipe = cg.Pipeline([plan], [cg.FIT_COLD], slots_per_stream=slots, max_burst_frames=burst,
+                       lanes=lanes, host_ring=True)
+    _log("phase C_paced_2.2GBps_host_copy ...")
+    t0 = time.perf_counter()
+    due, seq, dropped = t0, 0, 0
+    secs = 20.0
+    while time.perf_counter() - t0 < secs:
+        if time.perf_counter() < due:
+            continue
+        try:
+            pipe.put(0, pool_np[seq % n_pool], seq)
+        except cg.RingFull:
+            dropped += 1
+        seq += 1
+        due += bb / 2.2e9
+    pipe.drain(120000)
+    st = pipe.stats()
+    pipe.close()
+    out["C_paced_2.2GBps_host_copy"] = {"seconds": secs, "bursts": st["bursts"],
+                                        "GBps": st["bursts"] * bb / secs / 1e9,
+                                        "dropped": dropped, "overflows": st["overflows"],
+                                        "lat_p50_ms": st["lat_p50_ms"],
+                                        "lat_p99_ms": st["lat_p99_ms"],
+                                        "dev_lat_p50_ms": st["dev_lat_p50_ms"]}
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        pipe = cg.Pipeline([plan], [cg.FIT_COLD], slots_per_stream=4, max_burst_frames=burst,
+                           lanes=lanes, host_ring=True, keep_results=True)
+        for j in range(4):
+            pipe.put(0, pool_np[j], j)
+        pipe.drain(120000)
+        ok = tot = 0
+        t0 = time.perf_counter()
+        for j in range(4):
+            r = pipe.read(0)
+            rows = np.arange(j, burst, 64)
+            y = oracle.normalize(oracle.tooth_magnitudes(pool_np[j], spec.bins), ref)
+            p0 = oracle.initial_guess(y)
+            p_or, _, st_or, _ = oracle.lm_fit_batch(y[rows], p0[rows])
+            conv = st_or == 0
+            err = np.abs(r[1][rows, 0] - p_or[:, 0]) / np.abs(p_or[:, 1])
+            ok += int(np.count_nonzero(err[conv] <= 1e-3))
+            tot += int(conv.sum())
+        pipe.close()
+        parity = {"sample": "every 64th frame of four bursts", "frames": tot,
+                  "centre_within_1e-3_fwhm": ok / max(tot, 1),
+                  "oracle_seconds": time.perf_counter() - t0}
+    a = out["A_max_rate_in_place"]
+    line = {"metric": METRIC, "value": a["GBps"], "unit": "GB/s", "n_gpus": 1,
+            "steps": int(a["bursts"]), "warmup": slots,
+            "ms_per_step": 1e3 * a["seconds"] / max(1.0, a["bursts"]),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"host-streamed ingest: one paper-rate stream, bursts of "
+                                   f"{burst} x {n} int16 (128 MiB) through a pinned host ring "
+                                   f"of {slots} slots, copy stream + {lanes} compute lanes, "
+                                   f"cold-start fit; PCIe-inclusive",
+                       "burst_frames": burst, "slots": slots, "lanes": lanes},
+            "spectra_per_s": a["GBps"] * 1e9 / (2 * n), "phases": out}
+    if parity is not None:
+        line["parity"] = parity
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
 def multistream_parity(args, torch, cg, dev, specs, plans, pools, gen, w, tune):
     """Accuracy leg of the multi-stream workload: two bursts per stream
     through a pipeline that keeps its results, and a fixed 1-in-64 frame
@@ -594,7 +873,8 @@ def main():
     ap.add_argument("--frames", type=int, default=65536)
     ap.add_argument("--cpu-frames", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["paper_rate", "precision", "multistream", "warm"],
+    ap.add_argument("--workload", choices=["paper_rate", "precision", "multistream", "warm",
+                                           "fano", "host_ingest"],
                     default="paper_rate",
                     help="paper_rate: the headline line; precision: 131072 x 4096 frames, one "
                          "line per tooth-DFT form (FFT and the three matrix-core forms); "
@@ -643,6 +923,10 @@ def main():
         return precision_forms(args, torch, cg, dev)
     if args.workload == "multistream":
         return multistream(args, torch, cg, dev)
+    if args.workload == "fano":
+        return fano_workload(args, torch, cg, dev)
+    if args.workload == "host_ingest":
+        return host_ingest(args, torch, cg, dev)
     spec = synth.spec_paper_rate()
     nf, n, k = args.frames, spec.n, spec.k
     _log(f"generating {args.pool} batches of {nf} x {n} int16 ...")

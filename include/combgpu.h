@@ -72,6 +72,7 @@ typedef int32_t cg_status;
 #define CG_FIT_COLD      0x00u /* 7x7 median start point, full LM (default)     */
 #define CG_FIT_WARM_MLP  0x10u /* learned warm start + 2-iteration polish       */
 #define CG_FIT_NONE      0x20u /* stop after the normalised spectra             */
+#define CG_FIT_FANO      0x30u /* the paper's boxed Fano fit (cg_set_fano)      */
 #define CG_FIT_MASK      0xF0u
 
 /* Supported sizes. */
@@ -141,7 +142,8 @@ cg_status cg_process_batch(cg_plan* plan, const int16_t* frames, int64_t n_frame
  *   out_chi2    device float32[n_frames] final sum of squared residuals.
  *   out_teeth   device float32[n_frames][n_teeth] raw amplitudes |X[k_i]|.
  *   out_y       device float32[n_frames][n_teeth] normalised spectra.
- *   flags       one CG_DFT_* form OR one CG_FIT_* form.
+ *   flags       one CG_DFT_* form OR one CG_FIT_* form (CG_FIT_FANO: the
+ *               paper's boxed Fano fit, see cg_set_fano).
  *   workspace   device buffer of >= cg_workspace_bytes() bytes, or NULL to use
  *               the plan's own (then workspace_bytes is ignored).
  * out_params may be NULL only with CG_FIT_NONE.
@@ -167,8 +169,9 @@ cg_status cg_process_batch_ex(cg_plan* plan, const int16_t* frames, int64_t n_fr
  * hipFree, no allocating library routine.
  *   frames, out_params, out_iters, out_status, out_chi2, flags, stream as for
  *   cg_process_batch_ex (out_teeth / out_y are not offered); flags must name
- *   the FFT form (CG_DFT_FFT) with CG_FIT_COLD or CG_FIT_WARM_MLP (the
- *   matrix-core forms build a basis on first use, which allocates).
+ *   the FFT form (CG_DFT_FFT) with CG_FIT_COLD, CG_FIT_WARM_MLP or
+ *   CG_FIT_FANO (the matrix-core forms build a basis on first use, which
+ *   allocates).
  * Needs cg_workspace_bytes(plan, n_frames) <= CG_STATIC_SCRATCH_BYTES (for
  * 220 teeth: up to 72 000 frames); larger batches get CG_ERR_WORKSPACE and
  * nothing is enqueued.  The array's address on a device is resolved when a
@@ -256,6 +259,33 @@ cg_status cg_start_points(cg_plan* plan, const float* median, int64_t n_frames, 
 cg_status cg_fit_spectra(cg_plan* plan, const float* y, const float* p0, int64_t n_frames,
                          int32_t max_iter, float* out_params, int32_t* out_iters,
                          int32_t* out_status, float* out_chi2, void* stream);
+
+/*
+ * The paper's own fit (CG_FIT_FANO; paper, Data Capture and Processing: a
+ * five-parameter asymmetric Fano lineshape, only the centre free, scale and
+ * extent held within about +-10 % of pre-computed averages, asymmetry and
+ * width fixed to values measured for the device, <= 20 iterations,
+ * tolerance 1e-6):
+ *   y(x) = scale * (1 - extent * (1 + u/asymmetry)^2 / (1 + u^2)),
+ *   u = 2 (x - centre) / width,
+ * fitted by Levenberg-Marquardt over (centre, extent, scale) with extent in
+ * [0.9, 1.1] * depth_avg and scale in [0.9, 1.1] * scale_avg: a boxed
+ * parameter on a bound whose gradient points out of the box is held for the
+ * step and every trial point is clipped into the box.  Start point: the
+ * centre of the 7x7-median initializer (cg_init_spectra), extent and scale
+ * at their averages.  Schedule and statuses as the Lorentzian fit.  Output
+ * parameters (centre, width (the fixed value), extent, scale).
+ * cg_set_fano: width > 0, |asymmetry| >= 1e-3, averages > 0, all finite
+ * (host doubles; CG_ERR_INVALID_ARG otherwise).  cg_fit_fano: the fit alone
+ * on normalised spectra y (device float32 [n_frames][n_teeth]) from start
+ * points p0 (device float32 [n_frames][4], column 0 used), outputs as
+ * cg_fit_spectra; CG_ERR_STATE before cg_set_fano.
+ */
+cg_status cg_set_fano(cg_plan* plan, double width, double asymmetry, double depth_avg,
+                      double scale_avg);
+cg_status cg_fit_fano(cg_plan* plan, const float* y, const float* p0, int64_t n_frames,
+                      int32_t max_iter, float* out_params, int32_t* out_iters,
+                      int32_t* out_status, float* out_chi2, void* stream);
 
 /*
  * Learned warm start (CG_FIT_WARM_MLP).  A network 220 -> 256 -> 256 -> 4 with
@@ -369,15 +399,38 @@ cg_status cg_get_tuning(const cg_plan* plan, int32_t knob, int32_t* value);
  */
 typedef struct cg_pipeline cg_pipeline;
 #define CG_PIPE_MAX_STREAMS  64
+#define CG_PIPE_MAX_LANES    8
 #define CG_PIPE_KEEP_RESULTS 0x1u
 #define CG_PIPE_DRY_RUN      0x2u
+#define CG_PIPE_HOST_RING    0x4u
 cg_status cg_pipeline_create(int32_t n_streams, cg_plan* const* plans, const uint32_t* fit_flags,
                              int32_t slots_per_stream, int32_t max_burst_frames,
                              uint32_t options, double dry_us_per_frame, cg_pipeline** out);
+/*
+ * As cg_pipeline_create, with lanes_per_stream (1..CG_PIPE_MAX_LANES) compute
+ * lanes (HIP streams) per stream: consecutive bursts of a stream go to the
+ * lanes in turn and can run at the same time and complete out of order
+ * (cg_pipeline_read still hands them out in publish order).  fit_flags may
+ * also be CG_FIT_FANO (after cg_set_fano on the plan).
+ * CG_PIPE_HOST_RING (paper, Data Capture and Processing: digitiser -> ring
+ * buffer in host memory -> GPU): every slot also owns a pinned host frame
+ * buffer; cg_pipeline_acquire returns that host buffer, and the dispatcher
+ * copies each published burst host -> device on the stream's own copy
+ * stream, the burst's graph waiting for the copy, so copies of later bursts
+ * overlap the kernels of earlier ones; cg_pipeline_put then copies src (host
+ * memory) into the slot on the calling thread.  The throughput counters then
+ * include the PCIe transfer.
+ */
+cg_status cg_pipeline_create_ex(int32_t n_streams, cg_plan* const* plans,
+                                const uint32_t* fit_flags, int32_t slots_per_stream,
+                                int32_t max_burst_frames, uint32_t options,
+                                int32_t lanes_per_stream, double dry_us_per_frame,
+                                cg_pipeline** out);
 /* Stops the dispatcher after the queued bursts completed, frees everything. */
 cg_status cg_pipeline_destroy(cg_pipeline* pipe);
 /* Take a free slot of `stream` for writing: *frames receives its device buffer
- * int16 [max_burst_frames][frame_len].  CG_ERR_RING_FULL (counted as an
+ * int16 [max_burst_frames][frame_len] (with CG_PIPE_HOST_RING: its pinned
+ * host buffer).  CG_ERR_RING_FULL (counted as an
  * overflow) when every slot is queued, running or holding unread results. */
 cg_status cg_pipeline_acquire(cg_pipeline* pipe, int32_t stream, int32_t* slot,
                               int16_t** frames);
@@ -391,9 +444,10 @@ cg_status cg_pipeline_publish(cg_pipeline* pipe, int32_t stream, int32_t slot, i
  * before the burst's graph, so src must stay valid and unchanged until the
  * burst completes; a host source is best pinned (a pageable one makes the
  * dispatcher wait for the copy).  CG_ERR_RING_FULL as for
- * cg_pipeline_acquire. */
+ * cg_pipeline_acquire.  out_slot (may be NULL) receives the slot taken, so
+ * the caller can keep src alive until that slot is handed out again. */
 cg_status cg_pipeline_put(cg_pipeline* pipe, int32_t stream, const int16_t* src, int32_t n_frames,
-                          int64_t seq);
+                          int64_t seq, int32_t* out_slot);
 /* Pop the next burst of `stream` in publish order (CG_PIPE_KEEP_RESULTS),
  * once it has completed: bursts that complete before an earlier burst of
  * their stream are held until it has (the paper's re-sort of out-of-order
@@ -409,9 +463,10 @@ cg_status cg_pipeline_drain(cg_pipeline* pipe, int32_t timeout_ms);
  * int16 input, overflows, seconds from first publish to last completion,
  * host-clock latency p50, p99, max (ms), bytes/s, frames/s, GPU-clock
  * latency publish -> results p50, p99, max (ms), GPU-clock span graph start
- * -> results p50 (ms).  In dry-run mode the GPU-clock figures are the host
- * clock's. */
-#define CG_PIPE_NSTATS 14
+ * -> results p50 (ms), bursts that completed ahead of an earlier burst of
+ * their stream (re-sorted on read).  In dry-run mode the GPU-clock figures
+ * are the host clock's. */
+#define CG_PIPE_NSTATS 15
 cg_status cg_pipeline_stats(cg_pipeline* pipe, double* out, int32_t n_out);
 
 /*

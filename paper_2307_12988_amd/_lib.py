@@ -45,6 +45,8 @@ SIGNATURES = {
     "cg_set_tuning": (_i32, [_vp, _i32, _i32]),
     "cg_get_tuning": (_i32, [_vp, _i32, _pi32]),
     "cg_set_mlp": (_i32, [_vp, _pf32, _pf32, _pf32, _c.c_float]),
+    "cg_set_fano": (_i32, [_vp, _dbl, _dbl, _dbl, _dbl]),
+    "cg_fit_fano": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp]),
     "cg_set_polish_iters": (_i32, [_vp, _i32]),
     "cg_mlp_infer": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_mlp_trainer_create": (_i32, [_i32, _pf32, _c.POINTER(_vp)]),
@@ -54,10 +56,12 @@ SIGNATURES = {
     "cg_mlp_gradients": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cg_mlp_get_params": (_i32, [_vp, _pf32]),
     "cg_pipeline_create": (_i32, [_i32, _vp, _vp, _i32, _i32, _u32, _dbl, _c.POINTER(_vp)]),
+    "cg_pipeline_create_ex": (_i32, [_i32, _vp, _vp, _i32, _i32, _u32, _i32, _dbl,
+                                     _c.POINTER(_vp)]),
     "cg_pipeline_destroy": (_i32, [_vp]),
     "cg_pipeline_acquire": (_i32, [_vp, _i32, _pi32, _c.POINTER(_vp)]),
     "cg_pipeline_publish": (_i32, [_vp, _i32, _i32, _i32, _i64]),
-    "cg_pipeline_put": (_i32, [_vp, _i32, _vp, _i32, _i64]),
+    "cg_pipeline_put": (_i32, [_vp, _i32, _vp, _i32, _i64, _pi32]),
     "cg_pipeline_read": (_i32, [_vp, _i32, _pf32, _pi32, _i32, _pi32, _c.POINTER(_i64)]),
     "cg_pipeline_drain": (_i32, [_vp, _i32]),
     "cg_pipeline_stats": (_i32, [_vp, _c.POINTER(_dbl), _i32]),

@@ -259,7 +259,7 @@ cg_status process_impl(cg_plan* p, const int16_t* frames, int64_t nf, float* out
   const uint32_t dft = flags & CG_DFT_MASK;
   const uint32_t fit = flags & CG_FIT_MASK;
   if (dft > CG_DFT_MFMA_FP16X2) return CG_ERR_INVALID_ARG;
-  if (fit != CG_FIT_COLD && fit != CG_FIT_WARM_MLP && fit != CG_FIT_NONE)
+  if (fit != CG_FIT_COLD && fit != CG_FIT_WARM_MLP && fit != CG_FIT_NONE && fit != CG_FIT_FANO)
     return CG_ERR_INVALID_ARG;
   if (nf == 0) return CG_OK;
   if (fit != CG_FIT_NONE && !out_params) return CG_ERR_NULL;
@@ -283,6 +283,10 @@ cg_status process_impl(cg_plan* p, const int16_t* frames, int64_t nf, float* out
   }
   if (fit == CG_FIT_WARM_MLP && !p->mlp) {
     cg::set_detail("learned warm start needs cg_set_mlp first");
+    return CG_ERR_STATE;
+  }
+  if (fit == CG_FIT_FANO && !p->fano_set) {
+    cg::set_detail("the Fano fit needs cg_set_fano first");
     return CG_ERR_STATE;
   }
   const hipStream_t s = cg::pick(p, stream);
@@ -346,6 +350,11 @@ cg_status process_impl(cg_plan* p, const int16_t* frames, int64_t nf, float* out
   }
   e = cg::launch_median_start(y, nf, p->k, nullptr, p0, s);
   if (e != hipSuccess) return hip_fail(e, "median/start launch");
+  if (fit == CG_FIT_FANO) {
+    e = cg::launch_fano(p, y, p0, nf, 20, out_params, out_iters, out_status, out_chi2, s);
+    if (e != hipSuccess) return hip_fail(e, "fano launch");
+    return CG_OK;
+  }
   e = cg::launch_lm(y, p0, nf, p->k, 20, out_params, out_iters, out_status, out_chi2, s,
                     p->lm_chunk, nullptr, nullptr, p->lm_lanes);
   if (e != hipSuccess) return hip_fail(e, "lm launch");
@@ -462,6 +471,40 @@ cg_status cg_fit_spectra(cg_plan* p, const float* y, const float* p0, int64_t nf
   hipError_t e = cg::launch_lm(y, p0, nf, p->k, max_iter, out_params, out_iters, out_status,
                                out_chi2, s, p->lm_chunk, nullptr, nullptr, p->lm_lanes);
   if (e != hipSuccess) return hip_fail(e, "lm launch");
+  return CG_OK;
+}
+
+cg_status cg_set_fano(cg_plan* p, double width, double asymmetry, double depth_avg,
+                      double scale_avg) {
+  if (!p) return CG_ERR_NULL;
+  if (!std::isfinite(width) || !(width > 0.0) || !std::isfinite(asymmetry) ||
+      !(std::fabs(asymmetry) >= 1e-3) || !std::isfinite(depth_avg) || !(depth_avg > 0.0) ||
+      !std::isfinite(scale_avg) || !(scale_avg > 0.0)) {
+    cg::set_detail("width > 0, |asymmetry| >= 1e-3 and averages > 0, all finite");
+    return CG_ERR_INVALID_ARG;
+  }
+  p->fano_w = width;
+  p->fano_q = asymmetry;
+  p->fano_dbar = depth_avg;
+  p->fano_bbar = scale_avg;
+  p->fano_set = true;
+  return CG_OK;
+}
+
+cg_status cg_fit_fano(cg_plan* p, const float* y, const float* p0, int64_t nf, int32_t max_iter,
+                      float* out_params, int32_t* out_iters, int32_t* out_status,
+                      float* out_chi2, void* stream) {
+  if (!p || !out_params) return CG_ERR_NULL;
+  if (nf < 0 || max_iter < 1 || max_iter > CG_MAX_ITER) return CG_ERR_INVALID_ARG;
+  if (!p->fano_set) {
+    cg::set_detail("the Fano fit needs cg_set_fano first");
+    return CG_ERR_STATE;
+  }
+  if (nf == 0) return CG_OK;
+  if (!y || !p0) return CG_ERR_NULL;
+  hipError_t e = cg::launch_fano(p, y, p0, nf, max_iter, out_params, out_iters, out_status,
+                                 out_chi2, cg::pick(p, stream));
+  if (e != hipSuccess) return hip_fail(e, "fano launch");
   return CG_OK;
 }
 

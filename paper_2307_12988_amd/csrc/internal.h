@@ -32,6 +32,10 @@ struct cg_plan {
   int32_t lm_lanes = 0;        // lanes per spectrum in the fit kernel (0 = auto, 8, 16)
   int32_t fft_cap = 0;         // tuned cap on the FFT grid (0 = every resident block)
   int32_t polish_iters = 2;    // LM iterations from the network's start point
+  // Fano fit (CG_FIT_FANO): fixed width and asymmetry, averages of extent and
+  // scale (the box is +-10 % of them)
+  bool fano_set = false;
+  double fano_w = 0.0, fano_q = 0.0, fano_dbar = 0.0, fano_bbar = 0.0;
   int32_t fft_blocks = 0;      // resident blocks of the FFT kernel on the device (0 = no cap)
   // tooth-DFT bases for the matrix-core forms, [ceil(k/64)*64][n], built on
   // first use: bf16 cos_hi, cos_lo, sin_hi, sin_lo / fp16 cos, sin
@@ -97,6 +101,11 @@ hipError_t launch_lm(const float* y, const float* p0, int64_t n_frames, int k, i
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
                      int chunk = 0, const int32_t* dev_n = nullptr,
                      int32_t* zero_count = nullptr, int lanes = 0);
+// The paper's Fano fit from the start centres p0[f][0] (plan's fixed width,
+// asymmetry and box); hipErrorInvalidValue if the plan has no Fano settings.
+hipError_t launch_fano(const cg_plan* p, const float* y, const float* p0, int64_t n_frames,
+                       int max_iter, float* params, int32_t* iters, int32_t* status,
+                       float* chi2, hipStream_t s, const int32_t* dev_n = nullptr);
 // Indexed form: fit frames idx[0..*count) (count read on the device, at most
 // n_cap); every reported status is replaced by status_code.
 hipError_t launch_lm_indexed(const float* y, const float* p0, const int32_t* idx,

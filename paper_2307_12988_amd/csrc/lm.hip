@@ -31,6 +31,7 @@
 // not increase; converged when an accepted step lowers chi2 by at most
 // 1e-6 * chi2_old or chi2 <= 1e-30; a non-positive-definite damped matrix
 // stops the fit as singular.
+#include "fp64.h"
 #include "internal.h"
 #include "wave.h"
 
@@ -42,32 +43,6 @@ struct Sums {
   float g[4];    // J^T r
   double chi2;
 };
-
-__device__ __forceinline__ double rcp_d(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
-__device__ __forceinline__ double rsq_d(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  // Newton for 1/sqrt: r <- r (3 - x r^2) / 2
-  double h = 0.5 * x;
-  r = r * fma(-h * r, r, 1.5);
-  r = r * fma(-h * r, r, 1.5);
-  return r;
-}
-
-// One Newton step on the hardware reciprocal: the per-tooth denominators are
-// >= 1 and the hardware estimate is good to far more than half the FP64
-// mantissa, so one step leaves an error well below what the FP64 residuals
-// need.
-__device__ __forceinline__ double rcp1_d(double x) {
-  const double r = __builtin_amdgcn_rcp(x);
-  return fma(r, fma(-x, r, 1.0), r);
-}
 
 // Sums over the group's teeth at one parameter point (a group of G lanes,
 // Q = ceil(k / G) slots per lane).  The arithmetic is the same for every lane; teeth past the last

@@ -31,7 +31,8 @@
 //   results out in publish order (a burst that completes early waits for
 //   the earlier ones of its stream, as the paper re-sorts batches).
 // * Latency: the graph stamps the GPU's constant-rate wall clock when it
-//   starts and after the results are written.  The host clock and the GPU
+//   starts and after the results are written (with the host ring, a stamp
+//   on the copy stream ahead of the copy takes the start's place below).  The host clock and the GPU
 //   clock are tied by the smallest (graph start - launch call) seen in the
 //   last 0.1-0.2 s (a launch cannot start before it is issued, and when the
 //   GPU has spare queues the quickest launches start within microseconds),
@@ -39,6 +40,15 @@
 //   written is then read off the GPU's own clock.  Under a full load the
 //   quickest start may itself wait, which biases this figure low; the
 //   host-clock publish -> completion-seen latency is kept beside it.
+// * Host ring (CG_PIPE_HOST_RING): the paper's data path, digitiser -> host
+//   ring -> GPU.  Each slot also owns a pinned host frame buffer, which
+//   cg_pipeline_acquire hands out; the dispatcher copies a published burst to
+//   the device on the stream's copy stream, and the burst's graph waits for
+//   that copy on one of the stream's compute lanes, so copies of later
+//   bursts overlap earlier bursts' kernels.
+// * Lanes: with L > 1 compute lanes (HIP streams) per stream, consecutive
+//   bursts of a stream go to the lanes in turn and may complete out of
+//   order; cg_pipeline_read still hands them out in publish order.
 // * Dry run (CG_PIPE_DRY_RUN): the same bookkeeping with no device work; a
 //   burst "completes" after dry_us_per_frame * n microseconds.  Used to test
 //   overflow handling and ordering on machines without a GPU.
@@ -72,6 +82,8 @@ struct Burst {
 
 struct PipeSlot {
   int16_t* frames = nullptr;
+  int16_t* h_frames = nullptr;  // pinned host frame buffer (host ring only)
+  hipEvent_t copied = nullptr;  // host ring: the burst's copy has landed
   int32_t* n_dev = nullptr;
   int32_t* n_host = nullptr;  // pinned
   int32_t* n_host_dev = nullptr;  // device view of n_host
@@ -89,7 +101,8 @@ struct PipeSlot {
   int32_t* h_status = nullptr;  // pinned
   float* h_params_dev = nullptr;   // device views of the pinned results
   int32_t* h_status_dev = nullptr;
-  unsigned long long* h_ts = nullptr;      // pinned: GPU clock at graph start, results written
+  unsigned long long* h_ts = nullptr;      // pinned: GPU clock at graph start, results written,
+                                           // copy start (host ring)
   unsigned long long* h_ts_dev = nullptr;  // device view of h_ts
   const void* src = nullptr;  // copy source handed in by cg_pipeline_put (or null)
   size_t src_bytes = 0;
@@ -98,6 +111,7 @@ struct PipeSlot {
   hipEvent_t done = nullptr;
   int state = FREE;
   int64_t seq = 0;
+  int64_t ordinal = 0;  // publish order within the stream
   int32_t n = 0;
   double t_pub = 0.0, t_launch = 0.0, t_done = 0.0;
 };
@@ -105,10 +119,15 @@ struct PipeSlot {
 struct PipeStream {
   cg_plan* plan = nullptr;
   uint32_t flags = 0;
-  hipStream_t hs = nullptr;
+  hipStream_t hs = nullptr;            // lane 0 (captures the slot graphs)
+  std::vector<hipStream_t> lanes;      // compute lanes (lanes[0] == hs)
+  hipStream_t copy = nullptr;          // host ring: host -> device copies
+  int next_lane = 0;
   std::vector<PipeSlot> slots;
   int cursor = 0;
   int64_t last_seq_read = -1;
+  int64_t published_count = 0;
+  std::deque<int64_t> pending;  // ordinals published and not yet completed
   std::deque<int> published;  // slot indices in publish order (read order)
   int64_t bursts = 0, frames = 0;
 };
@@ -118,6 +137,7 @@ struct PipeStream {
 struct cg_pipeline {
   bool dry = false;
   bool keep = false;
+  bool host_ring = false;
   double dry_us = 0.0;
   int device = 0;
   int cap = 0;
@@ -131,6 +151,7 @@ struct cg_pipeline {
   bool failed = false;
   std::string fail_detail;
   int64_t overflows = 0, bursts = 0, frames = 0;
+  int64_t out_of_order = 0;  // bursts completed ahead of an earlier one of their stream
   double bytes = 0.0;
   double t_first = -1.0, t_last = 0.0;
   std::vector<float> lat_ms;      // host clock: publish -> completion seen
@@ -160,23 +181,28 @@ __global__ void count_in_kernel(const int32_t* __restrict__ host_n, int32_t* __r
   n[0] = host_n[0];
 }
 
-// Runs after the results kernel on the same stream: the GPU clock once the
-// burst's results are in host memory.
-__global__ void stamp_done_kernel(unsigned long long* __restrict__ ts) {
-  ts[1] = (unsigned long long)wall_clock64();
+// Host ring: the GPU clock when the burst's copy starts on the copy stream.
+__global__ void stamp_kernel(unsigned long long* __restrict__ ts) {
+  ts[2] = (unsigned long long)wall_clock64();
 }
 
+// One block copies the burst's results to pinned host memory, makes the
+// stores visible system-wide, then stamps the GPU clock: results written.
 __global__ __launch_bounds__(256) void results_out_kernel(const int32_t* __restrict__ n_dev,
                                                           int cap, const float4* __restrict__ params,
                                                           const int32_t* __restrict__ status,
                                                           float4* __restrict__ h_params,
-                                                          int32_t* __restrict__ h_status) {
+                                                          int32_t* __restrict__ h_status,
+                                                          unsigned long long* __restrict__ ts) {
   int n = *n_dev;
   n = n < cap ? n : cap;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
     h_params[i] = params[i];
     h_status[i] = status[i];
   }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) ts[1] = (unsigned long long)wall_clock64();
 }
 
 hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
@@ -204,19 +230,17 @@ hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
   } else {
     if (le == hipSuccess)
       le = launch_median_start(sl.y, cap, p->k, nullptr, sl.p0, s, nullptr, sl.n_dev);
-    if (le == hipSuccess)
+    if (le == hipSuccess && (ps.flags & CG_FIT_MASK) == CG_FIT_FANO)
+      le = launch_fano(p, sl.y, sl.p0, cap, 20, sl.params, sl.iters, sl.status, sl.chi2, s,
+                       sl.n_dev);
+    else if (le == hipSuccess)
       le = launch_lm(sl.y, sl.p0, cap, p->k, 20, sl.params, sl.iters, sl.status, sl.chi2, s,
                      p->lm_chunk, sl.n_dev, nullptr, p->lm_lanes);
   }
   if (le == hipSuccess) {
-    const int blocks = (cap + 255) / 256 < 64 ? (cap + 255) / 256 : 64;
-    hipLaunchKernelGGL(results_out_kernel, dim3(blocks), dim3(256), 0, s, sl.n_dev, cap,
+    hipLaunchKernelGGL(results_out_kernel, dim3(1), dim3(256), 0, s, sl.n_dev, cap,
                        reinterpret_cast<const float4*>(sl.params), sl.status,
-                       reinterpret_cast<float4*>(sl.h_params_dev), sl.h_status_dev);
-    le = hipGetLastError();
-  }
-  if (le == hipSuccess) {
-    hipLaunchKernelGGL(stamp_done_kernel, dim3(1), dim3(1), 0, s, sl.h_ts_dev);
+                       reinterpret_cast<float4*>(sl.h_params_dev), sl.h_status_dev, sl.h_ts_dev);
     le = hipGetLastError();
   }
   e = hipStreamEndCapture(s, &sl.graph);
@@ -226,6 +250,8 @@ hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
 }
 
 void free_slot(PipeSlot& sl) {
+  if (sl.copied) (void)hipEventDestroy(sl.copied);
+  if (sl.h_frames) (void)hipHostFree(sl.h_frames);
   if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
   if (sl.graph) (void)hipGraphDestroy(sl.graph);
   if (sl.done) (void)hipEventDestroy(sl.done);
@@ -237,10 +263,15 @@ void free_slot(PipeSlot& sl) {
   if (sl.h_ts) (void)hipHostFree(sl.h_ts);
 }
 
-hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
+hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap, bool host_ring) {
   const cg_plan* p = ps.plan;
   hipError_t e = hipMalloc(&sl.frames, (size_t)cap * p->n * sizeof(int16_t));
   if (e != hipSuccess) return e;
+  if (host_ring) {
+    if ((e = hipHostMalloc(&sl.h_frames, (size_t)cap * p->n * sizeof(int16_t))) != hipSuccess)
+      return e;
+    if ((e = hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming)) != hipSuccess) return e;
+  }
   // one device block for the count, spectra, start points and results
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -267,8 +298,8 @@ hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
   if ((e = hipHostMalloc(&sl.n_host, sizeof(int32_t))) != hipSuccess) return e;
   if ((e = hipHostMalloc(&sl.h_params, (size_t)cap * 16)) != hipSuccess) return e;
   if ((e = hipHostMalloc(&sl.h_status, (size_t)cap * 4)) != hipSuccess) return e;
-  if ((e = hipHostMalloc(&sl.h_ts, 2 * sizeof(unsigned long long))) != hipSuccess) return e;
-  sl.h_ts[0] = sl.h_ts[1] = 0;
+  if ((e = hipHostMalloc(&sl.h_ts, 3 * sizeof(unsigned long long))) != hipSuccess) return e;
+  sl.h_ts[0] = sl.h_ts[1] = sl.h_ts[2] = 0;
   if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.n_host_dev), sl.n_host, 0)) !=
       hipSuccess)
     return e;
@@ -285,18 +316,34 @@ hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
   return capture_slot(ps, sl, cap);
 }
 
-// launch one burst (dispatcher thread, no lock held): the queued copy if any,
-// then the slot's graph and its completion event, all on the stream's own HIP
-// stream, which no other thread enqueues on
+// launch one burst (dispatcher thread, no lock held): the copy, then the
+// slot's graph and its completion event on the next compute lane of the
+// stream.  No other thread enqueues on the stream's HIP streams.
 hipError_t launch_burst(cg_pipeline* P, const Burst& q) {
   PipeStream& ps = P->st[q.stream];
   PipeSlot& sl = ps.slots[q.slot];
+  hipStream_t lane = ps.lanes[ps.next_lane];
+  ps.next_lane = (ps.next_lane + 1) % (int)ps.lanes.size();
   hipError_t e = hipSuccess;
-  if (sl.src) e = hipMemcpyAsync(sl.frames, sl.src, sl.src_bytes, hipMemcpyDefault, ps.hs);
+  const size_t bytes = (size_t)sl.n * ps.plan->n * sizeof(int16_t);
+  if (P->host_ring) {
+    // the host ring slot -> device on the copy stream (after a GPU-clock
+    // stamp, the earliest point of the burst the GPU sees); the lane waits
+    // for the copy
+    sl.t_launch = now_s();
+    hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(1), 0, ps.copy, sl.h_ts_dev);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(sl.frames, sl.h_frames, bytes, hipMemcpyHostToDevice, ps.copy);
+    if (e == hipSuccess) e = hipEventRecord(sl.copied, ps.copy);
+    if (e == hipSuccess) e = hipStreamWaitEvent(lane, sl.copied, 0);
+  } else if (sl.src) {
+    e = hipMemcpyAsync(sl.frames, sl.src, sl.src_bytes, hipMemcpyDefault, lane);
+  }
   *sl.n_host = sl.n;  // read by the graph's first kernel
-  sl.t_launch = now_s();
-  if (e == hipSuccess) e = hipGraphLaunch(sl.exec, ps.hs);
-  if (e == hipSuccess) e = hipEventRecord(sl.done, ps.hs);
+  if (!P->host_ring) sl.t_launch = now_s();
+  if (e == hipSuccess) e = hipGraphLaunch(sl.exec, lane);
+  if (e == hipSuccess) e = hipEventRecord(sl.done, lane);
   return e;
 }
 
@@ -310,6 +357,12 @@ void complete(cg_pipeline* P, const Burst& q, double t) {
   PipeStream& ps = P->st[q.stream];
   PipeSlot& sl = ps.slots[q.slot];
   sl.t_done = t;
+  if (!ps.pending.empty() && ps.pending.front() != sl.ordinal) P->out_of_order += 1;
+  for (auto it = ps.pending.begin(); it != ps.pending.end(); ++it)
+    if (*it == sl.ordinal) {
+      ps.pending.erase(it);
+      break;
+    }
   ps.bursts += 1;
   ps.frames += sl.n;
   P->bursts += 1;
@@ -323,7 +376,9 @@ void complete(cg_pipeline* P, const Burst& q, double t) {
   } else {
     const double g0 = (double)sl.h_ts[0] / P->clk_hz, g1 = (double)sl.h_ts[1] / P->clk_hz;
     // GPU clock minus host clock, bounded below by the launch-to-start gap
-    const double gap = g0 - sl.t_launch;
+    // (host ring: of the copy-stream stamp, since the graph waits for the copy)
+    const double gs = P->host_ring ? (double)sl.h_ts[2] / P->clk_hz : g0;
+    const double gap = gs - sl.t_launch;
     if (t - P->off_epoch > 0.1) {
       P->off_prev = P->off_cur;
       P->off_cur = 1e300;
@@ -412,15 +467,19 @@ using cg::hip_fail;
 
 extern "C" {
 
-cg_status cg_pipeline_create(int32_t n_streams, cg_plan* const* plans, const uint32_t* fit_flags,
-                             int32_t slots_per_stream, int32_t max_burst_frames, uint32_t options,
-                             double dry_us_per_frame, cg_pipeline** out) {
+cg_status cg_pipeline_create_ex(int32_t n_streams, cg_plan* const* plans,
+                                const uint32_t* fit_flags, int32_t slots_per_stream,
+                                int32_t max_burst_frames, uint32_t options,
+                                int32_t lanes_per_stream, double dry_us_per_frame,
+                                cg_pipeline** out) {
   if (!out) return CG_ERR_NULL;
   *out = nullptr;
   if (n_streams < 1 || n_streams > CG_PIPE_MAX_STREAMS || slots_per_stream < 1 ||
-      slots_per_stream > 64 || max_burst_frames < 1 || max_burst_frames > (1 << 20))
+      slots_per_stream > 64 || max_burst_frames < 1 || max_burst_frames > (1 << 20) ||
+      lanes_per_stream < 1 || lanes_per_stream > CG_PIPE_MAX_LANES)
     return CG_ERR_INVALID_ARG;
-  if ((options & ~(CG_PIPE_KEEP_RESULTS | CG_PIPE_DRY_RUN)) != 0u) return CG_ERR_INVALID_ARG;
+  if ((options & ~(CG_PIPE_KEEP_RESULTS | CG_PIPE_DRY_RUN | CG_PIPE_HOST_RING)) != 0u)
+    return CG_ERR_INVALID_ARG;
   const bool dry = (options & CG_PIPE_DRY_RUN) != 0u;
   if (dry && !(dry_us_per_frame >= 0.0)) return CG_ERR_INVALID_ARG;
   if (!dry) {
@@ -428,14 +487,16 @@ cg_status cg_pipeline_create(int32_t n_streams, cg_plan* const* plans, const uin
     for (int i = 0; i < n_streams; ++i) {
       if (!plans[i]) return CG_ERR_NULL;
       const uint32_t f = fit_flags[i];
-      if (f != CG_FIT_COLD && f != CG_FIT_WARM_MLP) return CG_ERR_INVALID_ARG;
+      if (f != CG_FIT_COLD && f != CG_FIT_WARM_MLP && f != CG_FIT_FANO) return CG_ERR_INVALID_ARG;
       if (f == CG_FIT_WARM_MLP && !plans[i]->mlp) return CG_ERR_STATE;
+      if (f == CG_FIT_FANO && !plans[i]->fano_set) return CG_ERR_STATE;
     }
   }
   cg_pipeline* P = new (std::nothrow) cg_pipeline();
   if (!P) return CG_ERR_OOM;
   P->dry = dry;
   P->keep = (options & CG_PIPE_KEEP_RESULTS) != 0u;
+  P->host_ring = !dry && (options & CG_PIPE_HOST_RING) != 0u;
   P->dry_us = dry_us_per_frame;
   P->cap = max_burst_frames;
   P->st.resize(n_streams);
@@ -452,9 +513,13 @@ cg_status cg_pipeline_create(int32_t n_streams, cg_plan* const* plans, const uin
     if (dry) continue;
     ps.plan = plans[i];
     ps.flags = fit_flags[i];
-    e = hipStreamCreateWithFlags(&ps.hs, hipStreamNonBlocking);
+    ps.lanes.assign(lanes_per_stream, nullptr);
+    for (int l = 0; l < lanes_per_stream && e == hipSuccess; ++l)
+      e = hipStreamCreateWithFlags(&ps.lanes[l], hipStreamNonBlocking);
+    if (e == hipSuccess) ps.hs = ps.lanes[0];
+    if (e == hipSuccess && P->host_ring) e = hipStreamCreateWithFlags(&ps.copy, hipStreamNonBlocking);
     for (int j = 0; j < slots_per_stream && e == hipSuccess; ++j)
-      e = cg::alloc_slot(ps, ps.slots[j], max_burst_frames);
+      e = cg::alloc_slot(ps, ps.slots[j], max_burst_frames, P->host_ring);
   }
   if (e != hipSuccess) {
     const cg_status st = hip_fail(e, "cg_pipeline_create");
@@ -464,6 +529,13 @@ cg_status cg_pipeline_create(int32_t n_streams, cg_plan* const* plans, const uin
   P->worker = std::thread(cg::dispatcher, P);
   *out = P;
   return CG_OK;
+}
+
+cg_status cg_pipeline_create(int32_t n_streams, cg_plan* const* plans, const uint32_t* fit_flags,
+                             int32_t slots_per_stream, int32_t max_burst_frames, uint32_t options,
+                             double dry_us_per_frame, cg_pipeline** out) {
+  return cg_pipeline_create_ex(n_streams, plans, fit_flags, slots_per_stream, max_burst_frames,
+                               options, 1, dry_us_per_frame, out);
 }
 
 cg_status cg_pipeline_destroy(cg_pipeline* P) {
@@ -480,7 +552,9 @@ cg_status cg_pipeline_destroy(cg_pipeline* P) {
     (void)hipDeviceSynchronize();
     for (auto& ps : P->st) {
       for (auto& sl : ps.slots) cg::free_slot(sl);
-      if (ps.hs) (void)hipStreamDestroy(ps.hs);
+      for (auto h : ps.lanes)
+        if (h) (void)hipStreamDestroy(h);
+      if (ps.copy) (void)hipStreamDestroy(ps.copy);
     }
   }
   delete P;
@@ -503,7 +577,7 @@ cg_status cg_pipeline_acquire(cg_pipeline* P, int32_t stream, int32_t* slot, int
       ps.slots[j].state = WRITING;
       ps.cursor = (j + 1) % r;
       *slot = j;
-      if (frames) *frames = ps.slots[j].frames;
+      if (frames) *frames = P->host_ring ? ps.slots[j].h_frames : ps.slots[j].frames;
       return CG_OK;
     }
   }
@@ -529,6 +603,8 @@ cg_status publish_burst(cg_pipeline* P, int32_t stream, int32_t slot, int32_t n_
     sl.t_pub = now_s();
     if (P->t_first < 0) P->t_first = sl.t_pub;
     sl.state = QUEUED;
+    sl.ordinal = ps.published_count++;
+    ps.pending.push_back(sl.ordinal);
     if (P->keep) ps.published.push_back(slot);
     P->queue.push_back(Burst{stream, slot});
   }
@@ -547,17 +623,26 @@ cg_status cg_pipeline_publish(cg_pipeline* P, int32_t stream, int32_t slot, int3
 }
 
 cg_status cg_pipeline_put(cg_pipeline* P, int32_t stream, const int16_t* src, int32_t n_frames,
-                          int64_t seq) {
+                          int64_t seq, int32_t* out_slot) {
+  if (out_slot) *out_slot = -1;
   if (!P || !src) return CG_ERR_NULL;
   if (P->dry) return CG_ERR_STATE;
   if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
   if (n_frames < 1 || n_frames > P->cap) return CG_ERR_INVALID_ARG;
   int32_t slot = -1;
-  cg_status st = cg_pipeline_acquire(P, stream, &slot, nullptr);
+  int16_t* dst = nullptr;
+  cg_status st = cg_pipeline_acquire(P, stream, &slot, &dst);
   if (st != CG_OK) return st;
+  if (out_slot) *out_slot = slot;
+  const size_t bytes = (size_t)n_frames * P->st[stream].plan->n * sizeof(int16_t);
+  if (P->host_ring) {
+    // the host ring slot is written here (src must then be host memory); the
+    // dispatcher copies it to the device
+    std::memcpy(dst, src, bytes);
+    return publish_burst(P, stream, slot, n_frames, seq, nullptr, 0);
+  }
   // the dispatcher issues the copy on the stream's HIP stream ahead of the
   // burst's graph
-  const size_t bytes = (size_t)n_frames * P->st[stream].plan->n * sizeof(int16_t);
   return publish_burst(P, stream, slot, n_frames, seq, src, bytes);
 }
 
@@ -644,6 +729,10 @@ cg_status cg_pipeline_stats(cg_pipeline* P, double* out, int32_t n_out) {
   out[11] = pct(dlat, 0.99);
   out[12] = vmax(dlat);
   out[13] = pct(dspan, 0.5);
+  {
+    std::lock_guard<std::mutex> lk(P->mu);
+    out[14] = (double)P->out_of_order;
+  }
   return CG_OK;
 }
 

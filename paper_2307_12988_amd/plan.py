@@ -22,6 +22,7 @@ DFT_MFMA_FP16X2 = 0x3
 FIT_COLD = 0x00
 FIT_WARM_MLP = 0x10
 FIT_NONE = 0x20
+FIT_FANO = 0x30
 
 FIT_CONVERGED, FIT_MAX_ITER, FIT_SINGULAR, FIT_FALLBACK = 0, 1, 2, 3
 TUNE_LM_CHUNK = 1
@@ -251,6 +252,32 @@ class Plan:
                                   float(noise_floor))
         _lib.check(st, "cg_set_mlp")
 
+    def set_fano(self, width: float, asymmetry: float, depth_avg: float, scale_avg: float):
+        """Fixed width and asymmetry and the averages of extent and scale of
+        the paper's Fano fit (FIT_FANO)."""
+        _lib.check(self._lib.cg_set_fano(self._h, float(width), float(asymmetry),
+                                         float(depth_avg), float(scale_avg)), "cg_set_fano")
+
+    def fit_fano(self, y, p0, max_iter: int = 20, out=None):
+        """The Fano fit alone from start centres p0[:, 0]."""
+        nf = int(y.shape[0])
+        yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")
+        pp = _dev_ptr(p0, torch.float32, (nf, 4), "p0")
+        dev = y.device
+        if out is None:
+            out = (torch.empty((nf, 4), dtype=torch.float32, device=dev),
+                   torch.empty((nf,), dtype=torch.int32, device=dev),
+                   torch.empty((nf,), dtype=torch.int32, device=dev),
+                   torch.empty((nf,), dtype=torch.float32, device=dev))
+        params, iters, status, chi2 = out
+        st = self._lib.cg_fit_fano(self._h, yp, pp, nf, int(max_iter),
+                                   _dev_ptr(params, torch.float32, (nf, 4), "params"),
+                                   _dev_ptr(iters, torch.int32, (nf,), "iters"),
+                                   _dev_ptr(status, torch.int32, (nf,), "status"),
+                                   _dev_ptr(chi2, torch.float32, (nf,), "chi2"), _stream(dev))
+        _lib.check(st, "cg_fit_fano")
+        return params, iters, status, chi2
+
     def set_polish_iters(self, iters: int):
         """LM iterations from the network's start point in the learned warm
         start (default 2; 20, the cold start's cap, makes it a full fit)."""
@@ -396,9 +423,10 @@ class Trainer:
 
 PIPE_KEEP_RESULTS = 0x1
 PIPE_DRY_RUN = 0x2
+PIPE_HOST_RING = 0x4
 STATS_FIELDS = ("bursts", "frames", "bytes", "overflows", "seconds", "lat_p50_ms", "lat_p99_ms",
                 "lat_max_ms", "bytes_per_s", "frames_per_s", "dev_lat_p50_ms", "dev_lat_p99_ms",
-                "dev_lat_max_ms", "dev_span_p50_ms")
+                "dev_lat_max_ms", "dev_span_p50_ms", "out_of_order")
 
 
 class RingFull(_lib.CombGpuError):
@@ -410,9 +438,13 @@ class Pipeline:
     `fit_flags` per stream; in dry-run mode pass `n_streams` instead."""
 
     def __init__(self, plans=None, fit_flags=None, slots_per_stream=4, max_burst_frames=4096,
-                 keep_results=False, dry_run_us_per_frame=None, n_streams=None):
+                 keep_results=False, dry_run_us_per_frame=None, n_streams=None, lanes=1,
+                 host_ring=False):
         self._lib = _lib.load()
         opts = PIPE_KEEP_RESULTS if keep_results else 0
+        if host_ring:
+            opts |= PIPE_HOST_RING
+        self.host_ring = bool(host_ring)
         if dry_run_us_per_frame is not None:
             opts |= PIPE_DRY_RUN
             ns = int(n_streams)
@@ -425,16 +457,18 @@ class Pipeline:
             dry = 0.0
         self._plans = plans  # keep alive
         h = ctypes.c_void_p()
-        st = self._lib.cg_pipeline_create(ns, arr_p, arr_f, int(slots_per_stream),
-                                          int(max_burst_frames), opts, dry, ctypes.byref(h))
-        _lib.check(st, "cg_pipeline_create")
+        st = self._lib.cg_pipeline_create_ex(ns, arr_p, arr_f, int(slots_per_stream),
+                                             int(max_burst_frames), opts, int(lanes), dry,
+                                             ctypes.byref(h))
+        _lib.check(st, "cg_pipeline_create_ex")
+        self.frame_len = [p.frame_len for p in plans] if plans is not None else None
         self._h = h
         self.n_streams = ns
         self.max_burst = int(max_burst_frames)
         self.slots = int(slots_per_stream)
-        # sources of queued copies stay referenced until their slot has been
-        # recycled (bursts of one stream complete in order, so R puts later)
-        self._held = [[] for _ in range(ns)]
+        # the source of each slot's queued copy stays referenced until the
+        # slot is taken again (its burst has then completed)
+        self._held = [dict() for _ in range(ns)]
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -458,26 +492,46 @@ class Pipeline:
         _lib.check(st, "cg_pipeline_acquire")
         return slot.value, ptr.value
 
+    def acquire_host(self, stream: int):
+        """Host ring: (slot, numpy int16 view [max_burst_frames, frame_len] of
+        the slot's pinned host buffer) or raises RingFull."""
+        if not self.host_ring:
+            raise ValueError("acquire_host needs a pipeline created with host_ring=True")
+        slot, ptr = self.acquire(stream)
+        n = self.max_burst * self.frame_len[int(stream)]
+        buf = (ctypes.c_int16 * n).from_address(ptr)
+        return slot, np.frombuffer(buf, dtype=np.int16).reshape(self.max_burst, -1)
+
     def publish(self, stream: int, slot: int, n_frames: int, seq: int):
         _lib.check(self._lib.cg_pipeline_publish(self._h, int(stream), int(slot), int(n_frames),
                                                  int(seq)), "cg_pipeline_publish")
 
     def put(self, stream: int, frames, seq: int):
         """Copy a burst (torch int16 tensor on the GPU or pinned CPU tensor,
-        [n, frame_len], contiguous) into a free slot and publish it.  Raises
-        RingFull when the stream has no free slot."""
-        if not isinstance(frames, torch.Tensor) or frames.dtype != torch.int16 or \
-                frames.dim() != 2 or not frames.is_contiguous():
-            raise ValueError("frames must be a contiguous int16 torch tensor [n, frame_len]")
-        st = self._lib.cg_pipeline_put(self._h, int(stream), ctypes.c_void_p(frames.data_ptr()),
-                                       int(frames.shape[0]), int(seq))
+        [n, frame_len], contiguous; with the host ring a host numpy array or
+        CPU tensor, copied into the ring on this thread) into a free slot and
+        publish it.  Raises RingFull when the stream has no free slot."""
+        if isinstance(frames, np.ndarray):
+            if not self.host_ring:
+                raise ValueError("numpy sources need a host-ring pipeline")
+            if frames.dtype != np.int16 or frames.ndim != 2 or not frames.flags.c_contiguous:
+                raise ValueError("frames must be a C-contiguous int16 array [n, frame_len]")
+            ptr, nfr = frames.ctypes.data, int(frames.shape[0])
+        else:
+            if not isinstance(frames, torch.Tensor) or frames.dtype != torch.int16 or \
+                    frames.dim() != 2 or not frames.is_contiguous():
+                raise ValueError("frames must be a contiguous int16 torch tensor [n, frame_len]")
+            if self.host_ring and frames.is_cuda:
+                raise ValueError("a host-ring pipeline takes host frames")
+            ptr, nfr = frames.data_ptr(), int(frames.shape[0])
+        slot = ctypes.c_int32(-1)
+        st = self._lib.cg_pipeline_put(self._h, int(stream), ctypes.c_void_p(ptr), nfr, int(seq),
+                                       ctypes.byref(slot))
         if st == -9:
             raise RingFull(st, "cg_pipeline_put")
         _lib.check(st, "cg_pipeline_put")
-        held = self._held[int(stream)]
-        held.append(frames)
-        if len(held) > self.slots:
-            held.pop(0)
+        if not self.host_ring:
+            self._held[int(stream)][slot.value] = frames
 
     def read(self, stream: int):
         """Oldest completed burst of `stream`: (seq, params [n,4], status [n]) or None."""
@@ -495,7 +549,7 @@ class Pipeline:
 
     def drain(self, timeout_ms: int = 60000):
         _lib.check(self._lib.cg_pipeline_drain(self._h, int(timeout_ms)), "cg_pipeline_drain")
-        self._held = [[] for _ in range(self.n_streams)]
+        self._held = [dict() for _ in range(self.n_streams)]
 
     def stats(self):
         out = (ctypes.c_double * len(STATS_FIELDS))()
