@@ -51,10 +51,11 @@ SEED = 1
 # for the kernel sources they were taken on:
 # kernel -> (sources, sha256 prefix of their concatenation, read B, write B)
 TRAFFIC = {
-    "fft_teeth": (("fft_teeth.hip",), "c534d5e472cf9551", 131308.6 * 2 * 1024, 56323.2 * 1024),
+    "fft_teeth": (("fft_teeth.hip",), "c8c18ee7d4f30561", 131306.6 * 2 * 1024, 56323.6 * 1024),
     "median_start": (("median.hip", "wave.h"), "1ac469519e98187a", 39067.4 * 2 * 1024,
                      1024.0 * 1024),
-    "lm_fit": (("lm.hip", "wave.h"), "75aa0426e98ec94a", 28744.7 * 2 * 1024, 1810.9 * 1024),
+    "lm_fit": (("lm.hip", "wave.h", "fp64.h"), "920363e16bdc8fa4", 28744.6 * 2 * 1024,
+               1550.7 * 1024),
 }
 
 
@@ -83,14 +84,14 @@ def _gen(args):
     return b, bt.frames, bt.ref_frames, (bt.centre, bt.width)
 
 
-def make_pool(spec, nf, n_batches, workers, truth=False):
+def make_pool(spec, nf, n_batches, workers, truth=False, seed=SEED):
     """Synthetic batches (and, with truth, each batch's true dip centres and
     widths)."""
     frames = [None] * n_batches
     truths = [None] * n_batches
     ref = None
     with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-        for b, fr, rf, tr in ex.map(_gen, [(spec, nf, SEED, b) for b in range(n_batches)]):
+        for b, fr, rf, tr in ex.map(_gen, [(spec, nf, seed, b) for b in range(n_batches)]):
             frames[b] = fr
             truths[b] = tr
             ref = rf
@@ -354,9 +355,18 @@ def warm_forms(args, torch, cg, dev):
                                    "median_fwhm": float(np.median(err[conv]))}}
         # every frame of the first batch against the generator's true centre
         et = np.abs(r["params"][:, 0] - truths[0][0]) / truths[0][1]
+        out_mask = et > 1.0
         line["centre_vs_truth"] = {"frames": int(nf), "median_fwhm": float(np.median(et)),
                                    "p90_fwhm": float(np.percentile(et, 90)),
-                                   "p99_fwhm": float(np.percentile(et, 99))}
+                                   "p99_fwhm": float(np.percentile(et, 99)),
+                                   "p99.9_fwhm": float(np.percentile(et, 99.9)),
+                                   "rms_fwhm": float(np.sqrt(np.mean(et ** 2))),
+                                   "max_fwhm": float(et.max()),
+                                   "frames_beyond_1_fwhm": int(out_mask.sum()),
+                                   "their_status_counts":
+                                       np.bincount(r["status"][out_mask], minlength=4).tolist(),
+                                   "their_median_fitted_width": float(np.median(
+                                       r["params"][out_mask, 1])) if out_mask.any() else None}
         if orc is not None:
             m = orc["n"] - 3  # the oracle's slice ends at its own last frame
             oc = orc["status"][:m] == 0
@@ -873,8 +883,8 @@ def main():
     ap.add_argument("--frames", type=int, default=65536)
     ap.add_argument("--cpu-frames", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["paper_rate", "precision", "multistream", "warm",
-                                           "fano", "host_ingest"],
+    ap.add_argument("--workload", choices=["paper_rate", "tiny", "precision", "multistream",
+                                           "warm", "fano", "host_ingest"],
                     default="paper_rate",
                     help="paper_rate: the headline line; precision: 131072 x 4096 frames, one "
                          "line per tooth-DFT form (FFT and the three matrix-core forms); "
@@ -928,10 +938,15 @@ def main():
     if args.workload == "host_ingest":
         return host_ingest(args, torch, cg, dev)
     spec = synth.spec_paper_rate()
+    if args.workload == "tiny":
+        # the small plain workload (4096 x 1024-sample frames, 100 teeth)
+        spec = synth.spec_tiny()
+        args.frames, args.cpu_frames = 4096, 4096
     nf, n, k = args.frames, spec.n, spec.k
     _log(f"generating {args.pool} batches of {nf} x {n} int16 ...")
     t0 = time.perf_counter()
-    pool_np, ref_np = make_pool(spec, nf, args.pool, workers=min(args.pool, 8))
+    pool_np, ref_np = make_pool(spec, nf, args.pool, workers=min(args.pool, 8),
+                                seed=0 if args.workload == "tiny" else SEED)
     pool_np_0 = pool_np[0]
     _log(f"  {time.perf_counter() - t0:.1f} s")
     pool = [torch.from_numpy(fr).to(dev) for fr in pool_np]
@@ -1105,7 +1120,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"paper-rate comb stream: {nf} frames x {n} int16 samples per "
+        "config": {"workload": f"{'paper-rate' if spec.name == 'paper_rate' else spec.name} comb "
+                               f"stream: {nf} frames x {n} int16 samples per "
                                f"batch, {k} teeth, cold-start 7x7 median + LM (<=20 it)",
                    "frames_per_batch": nf, "frame_len": n, "n_teeth": k,
                    "pool_batches": args.pool, "pool_GiB": args.pool * nf * n * 2 / 2 ** 30,
