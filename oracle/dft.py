@@ -24,10 +24,11 @@ import numpy as np
 
 
 def frames_to_float(frames) -> np.ndarray:
-    """Cast int16 frames [F, N] to float64 (exact)."""
+    """Cast integer frames [F, N] (int16, or the paper's int8) to float64
+    (exact)."""
     x = np.asarray(frames)
-    if x.dtype != np.int16:
-        raise TypeError(f"frames must be int16, got {x.dtype}")
+    if x.dtype not in (np.int16, np.int8):
+        raise TypeError(f"frames must be int16 or int8, got {x.dtype}")
     if x.ndim != 2:
         raise ValueError("frames must be [n_frames, frame_len]")
     return x.astype(np.float64)

@@ -12,6 +12,7 @@ from .comb import (
     Batch,
     tooth_bins_paper_c1,
     tooth_bins_interleaved,
+    tooth_bins_paper_2200,
     make_batch,
     make_lorentzian_spectra,
     spec_tiny,
@@ -20,6 +21,7 @@ from .comb import (
     spec_learned,
     spec_multistream,
     spec_fano,
+    spec_paper8,
 )
 
 __all__ = [
@@ -27,6 +29,7 @@ __all__ = [
     "Batch",
     "tooth_bins_paper_c1",
     "tooth_bins_interleaved",
+    "tooth_bins_paper_2200",
     "make_batch",
     "make_lorentzian_spectra",
     "spec_tiny",
@@ -35,4 +38,5 @@ __all__ = [
     "spec_learned",
     "spec_multistream",
     "spec_fano",
+    "spec_paper8",
 ]

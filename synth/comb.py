@@ -47,6 +47,14 @@ def tooth_bins_paper_c1() -> np.ndarray:
     return np.abs(51 + 10 * n).astype(np.int32)
 
 
+def tooth_bins_paper_2200() -> np.ndarray:
+    """The paper's own comb: 220 teeth at beat frequencies |51 + 10 n| MHz,
+    n = -115 .. 104, on the 1 MHz bins of 2200-sample frames at 2.2 GS/s
+    (bins 1 .. 1099, all distinct: the two families end in 1 and in 9)."""
+    n = np.arange(-115, 105)
+    return np.abs(51 + 10 * n).astype(np.int32)
+
+
 def tooth_bins_interleaved(n_samples: int, n_teeth: int) -> np.ndarray:
     """Two interleaved tooth families on distinct integer bins below Nyquist.
 
@@ -92,6 +100,7 @@ class StreamSpec:
     asym_q: float = float("inf")       # Fano asymmetry (fano lineshape only)
     power_drift: float = 0.0           # laser-power drift of the baseline, +- fraction
     power_drift_hz: float = 1700.0
+    sample_dtype: str = "int16"        # "int16" or "int8" (then bits <= 8)
 
     @property
     def k(self) -> int:
@@ -225,6 +234,11 @@ def make_batch(spec: StreamSpec, n_frames: int, seed: int, batch_index: int = 0,
         clipped += c
 
     ref, _ = _quantise(gain * _reference_float(spec)[None, :], spec.bits)
+    if spec.sample_dtype == "int8":
+        if spec.bits > 8:
+            raise ValueError("int8 samples need bits <= 8")
+        out = out.astype(np.int8)
+        ref = ref.astype(np.int8)
     return Batch(frames=out, ref_frames=ref, centre=centre, width=width, depth=depth,
                  baseline=baseline, snr_db=snr, tilt=tilt, gain=gain, clipped=clipped,
                  first_frame=first, meta={"spec": spec.name, "seed": int(seed)})
@@ -294,6 +308,18 @@ def spec_fano() -> StreamSpec:
     return StreamSpec(name="fano", n=2048, fs=1.1e9, bins=tooth_bins_interleaved(2048, 220),
                       width=(8.03, 8.03), depth=(0.6, 0.6), snr_db=(20.0, 50.0),
                       lineshape="fano", asym_q=4.0, power_drift=0.05)
+
+
+def spec_paper8() -> StreamSpec:
+    """The paper's own ingest geometry: 8-bit samples at 2.2 GS/s in
+    2200-sample (1 us) frames, 220 teeth at |51 + 10 n| MHz (n = -115..104)
+    on 1 MHz bins, with the Fano dip of spec_fano (fixed width 8.03 teeth,
+    asymmetry 4, depth 0.6, +-5 % laser-power drift), centre +-10 teeth at
+    23.686 kHz, SNR U[20,50] dB before the 8-bit quantisation."""
+    return StreamSpec(name="paper8", n=2200, fs=2.2e9, bins=tooth_bins_paper_2200(),
+                      width=(8.03, 8.03), depth=(0.6, 0.6), snr_db=(20.0, 50.0),
+                      lineshape="fano", asym_q=4.0, power_drift=0.05, bits=8,
+                      sample_dtype="int8")
 
 
 def spec_multistream(seed: int = 100, n_streams: int = 16) -> Sequence[StreamSpec]:

@@ -167,3 +167,27 @@ def test_reference_is_mean_of_amplitudes_over_frames():
     assert not np.allclose(want, np.sqrt((per_frame ** 2).mean(axis=0)))
     coherent = np.abs(np.fft.rfft(frames.astype(np.float64), axis=1).mean(axis=0)[bins])
     assert abs(want[1] - coherent[1]) > 1.0
+
+
+def test_paper_geometry_2200_int8():
+    """The paper's frames: 2200 int8 samples at 2.2 GS/s, teeth |51 + 10 n| MHz
+    (n = -115..104) on distinct 1 MHz bins.  The DFT of int8 frames matches
+    numpy's FFT, and a noiseless 8-bit comb puts each tooth's amplitude at
+    A g N / 2 within the quantisation bound."""
+    bins = synth.tooth_bins_paper_2200()
+    assert len(bins) == 220 and len(np.unique(bins)) == 220
+    assert bins.min() == 1 and bins.max() == 1099
+    rng = np.random.default_rng(22)
+    fr = rng.integers(-128, 128, size=(3, 2200)).astype(np.int8)
+    re, im = oracle.dft_at_bins(fr, bins)
+    ref = np.fft.rfft(fr.astype(np.float64), axis=1)[:, bins]
+    assert np.max(np.abs((re + 1j * im) - ref)) <= 1e-12 * np.abs(ref).max() * np.sqrt(2200)
+    spec = synth.spec_paper8()
+    bt = synth.make_batch(spec, 4, seed=3, noise=False)
+    assert bt.frames.dtype == np.int8 and bt.frames.shape == (4, 2200)
+    m = oracle.tooth_magnitudes(bt.ref_frames, spec.bins)[0]
+    # a unit comb scaled by the gain: every tooth at g N / 2 up to the 8-bit
+    # rounding, whose error per bin is at most N/2 (|e_t| <= 1/2)
+    assert np.max(np.abs(m - bt.gain * 2200 / 2)) <= 2200 / 2
+    with pytest.raises(TypeError):
+        oracle.frames_to_float(fr.astype(np.int32))
