@@ -398,15 +398,20 @@ def fano_workload(args, torch, cg, dev):
     int16 samples of the Fano stream (fixed width 8.03 teeth, asymmetry 4,
     depth 0.6, +-5 % laser-power drift), FFT, tooth gather, normalisation,
     7x7-median start centre and the boxed Fano LM (extent and scale within
-    +-10 % of 0.6 and 1.0).  Same timing scheme as the headline workload."""
-    spec = synth.spec_fano()
+    +-10 % of 0.6 and 1.0).  Same timing scheme as the headline workload.
+    With --workload paper8: the paper's whole configuration, 8-bit
+    2200-sample frames at 2.2 GS/s (mixed-radix FFT), its |51 + 10 n| MHz
+    comb and the same Fano fit."""
+    spec = synth.spec_paper8() if args.workload == "paper8" else synth.spec_fano()
     nf, n, k = args.frames, spec.n, spec.k
     _log(f"generating {args.pool} batches of {nf} x {n} int16 (Fano stream) ...")
     pool_np, ref_np = make_pool(spec, nf, args.pool, workers=min(args.pool, 8))
     first_np = pool_np[0]
     pool = [torch.from_numpy(fr).to(dev) for fr in pool_np]
     del pool_np
-    plan = cg.Plan(n, spec.fs, spec.bins, np.ones(k, dtype=np.float32))
+    sbytes = np.dtype(first_np.dtype).itemsize
+    plan = cg.Plan(n, spec.fs, spec.bins, np.ones(k, dtype=np.float32),
+                   sample_type=spec.sample_dtype)
     ref = plan.reference_from_frames(torch.from_numpy(ref_np).to(dev)).cpu().numpy()
     plan.set_reference(ref)
     plan.set_fano(FANO_W, FANO_Q, FANO_DBAR, FANO_BBAR)
@@ -468,7 +473,7 @@ def fano_workload(args, torch, cg, dev):
         ms[nm] = ev[0].elapsed_time(ev[1]) / reps
     it_fit = fit_out[1].cpu().numpy()
     fit_tf = fano_flops(k, it_fit) / (ms["fano_fit"] * 1e-3) / 1e12
-    fft_gbs = nf * (2 * n + 4 * k) / (ms["fft_teeth"] * 1e-3) / 1e9
+    fft_gbs = nf * (sbytes * n + 4 * k) / (ms["fft_teeth"] * 1e-3) / 1e9
     dom = max(ms, key=ms.get)
     if dom == "fano_fit":
         roof = {"kernel": dom, "bound": "alu", "achieved": fit_tf, "peak": VALU_FP32_PEAK_TFLOPS,
@@ -481,13 +486,14 @@ def fano_workload(args, torch, cg, dev):
         ach = MEDIAN_OPS_PER_OUTPUT * nf * k / (ms[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": VALU_OPS_PEAK_TOPS,
                 "unit": "Top/s", "frac": ach / VALU_OPS_PEAK_TOPS, "traffic": None}
-    line = {"metric": METRIC, "value": nf * n * 2 * args.steps / wall / 1e9, "unit": "GB/s",
+    line = {"metric": METRIC, "value": nf * n * sbytes * args.steps / wall / 1e9, "unit": "GB/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": f"paper's Fano fit: {nf} frames x {n} int16 samples per batch, "
-                                   f"{k} teeth, width {FANO_W} and asymmetry {FANO_Q} fixed, extent "
-                                   f"and scale boxed +-10% of {FANO_DBAR} and {FANO_BBAR}",
+            "config": {"workload": f"paper's Fano fit: {nf} frames x {n} {spec.sample_dtype} "
+                                   f"samples per batch, {k} teeth, width {FANO_W} and asymmetry "
+                                   f"{FANO_Q} fixed, extent and scale boxed +-10% of {FANO_DBAR} "
+                                   f"and {FANO_BBAR}",
                        "frames_per_batch": nf, "frame_len": n, "n_teeth": k,
                        "pool_batches": args.pool, "streams": ns},
             "spectra_per_s": nf * args.steps / wall,
@@ -508,7 +514,7 @@ def fano_workload(args, torch, cg, dev):
         m = ns_cpu - 3
         conv = ora["status"][:m] == 0
         err = np.abs(params0[:m, 0] - ora["params"][:m, 0]) / FANO_W
-        line["cpu_baseline"] = {"value": ns_cpu * n * 2 / dt / 1e9, "unit": "GB/s",
+        line["cpu_baseline"] = {"value": ns_cpu * n * sbytes / dt / 1e9, "unit": "GB/s",
                                 "spectra_per_s": ns_cpu / dt, "cores": None, "kind": "oracle",
                                 "sample": f"first {ns_cpu} frames of batch 0 (FP64 oracle's "
                                           f"whole Fano path), {dt:.1f} s",
@@ -884,7 +890,7 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["paper_rate", "tiny", "precision", "multistream",
-                                           "warm", "fano", "host_ingest"],
+                                           "warm", "fano", "paper8", "host_ingest"],
                     default="paper_rate",
                     help="paper_rate: the headline line; precision: 131072 x 4096 frames, one "
                          "line per tooth-DFT form (FFT and the three matrix-core forms); "
@@ -933,7 +939,7 @@ def main():
         return precision_forms(args, torch, cg, dev)
     if args.workload == "multistream":
         return multistream(args, torch, cg, dev)
-    if args.workload == "fano":
+    if args.workload in ("fano", "paper8"):
         return fano_workload(args, torch, cg, dev)
     if args.workload == "host_ingest":
         return host_ingest(args, torch, cg, dev)

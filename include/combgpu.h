@@ -21,7 +21,9 @@
  * - `stream` is a hipStream_t passed as void*; NULL is HIP's null (default)
  *   stream.  Work is only enqueued on that stream: the call returns before the
  *   GPU finishes, and stream order is the only ordering with the caller's work.
- * - Arrays are row-major and contiguous: frames int16 [n_frames][frame_len];
+ * - Arrays are row-major and contiguous: frames [n_frames][frame_len] of the
+ *   plan's sample type (int16, or int8 for a plan made with
+ *   CG_SAMPLES_INT8), passed as void*;
  *   spectra float32 [n_frames][n_teeth]; parameters float32 [n_frames][4] in
  *   the order (centre, width, depth, baseline).
  * - Centre and width are in units of the tooth index (0 .. n_teeth-1, optical
@@ -78,12 +80,17 @@ typedef int32_t cg_status;
 /* Supported sizes. */
 #define CG_MIN_FRAME_LEN 512
 #define CG_MAX_FRAME_LEN 8192
+#define CG_PAPER_FRAME_LEN 2200 /* the paper's rows: 1 us at 2.2 GS/s          */
+
+/* Sample types of cg_create_plan_ex. */
+#define CG_SAMPLES_INT16 0
+#define CG_SAMPLES_INT8  1 /* the paper's 8-bit digitiser samples            */
 #define CG_MAX_TEETH     440
 #define CG_MAX_ITER      64
 
 /*
- * Create a plan for frames of `frame_len` samples (a power of two in
- * 512..8192) and `n_teeth` comb teeth (1..min(440, frame_len/2+1)).
+ * Create a plan for frames of `frame_len` int16 samples (a power of two in
+ * 512..8192, or 2200) and `n_teeth` comb teeth (1..min(440, frame_len/2+1)).
  *   fs            sample rate in Hz (> 0, finite); metadata only: bin k is
  *                 k*fs/frame_len Hz and frame f starts at f*frame_len/fs s.
  *   tooth_bins    host int32[n_teeth]: DFT bin of each tooth in optical
@@ -101,6 +108,23 @@ typedef int32_t cg_status;
  */
 cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins,
                          int32_t n_teeth, const float* ref_spectrum, cg_plan** out_plan);
+
+/*
+ * As cg_create_plan for frames of `sample_type` samples (paper, Data Capture
+ * and Processing: 8-bit integer samples cast to single precision on the GPU,
+ * rows of 2200 samples = 1 us at 2.2 GS/s).  frame_len is a power of two in
+ * 512..8192 for CG_SAMPLES_INT16, or CG_PAPER_FRAME_LEN (2200) for either
+ * type; 2200-sample frames go through a mixed-radix (4, 5, 5, 11) FFT of
+ * 1100 complex points.  The matrix-core DFT forms take int16 frames of a
+ * power-of-two length only (CG_ERR_UNSUPPORTED otherwise).  Errors as for
+ * cg_create_plan, CG_ERR_INVALID_ARG for an unknown sample type.
+ */
+cg_status cg_create_plan_ex(int32_t frame_len, double fs, const int32_t* tooth_bins,
+                            int32_t n_teeth, const float* ref_spectrum, int32_t sample_type,
+                            cg_plan** out_plan);
+
+/* Bytes per sample of the plan's frames (2 or 1). */
+cg_status cg_plan_sample_bytes(const cg_plan* plan, int32_t* bytes);
 
 /* Release a plan and everything it owns (NULL is allowed).  Synchronises the
  * device first. */
@@ -125,14 +149,15 @@ cg_status cg_workspace_bytes(const cg_plan* plan, int64_t n_frames, size_t* byte
  * Whole hot path for one batch: cast + frame, real FFT, tooth gather,
  * amplitude, division by the reference, 7x7 median start point and the
  * Levenberg-Marquardt fit (at most 20 iterations, tolerance 1e-6).
- *   frames      device int16[n_frames][frame_len].
+ *   frames      device [n_frames][frame_len] samples (int16, or int8 for a
+ *               CG_SAMPLES_INT8 plan).
  *   out_params  device float32[n_frames][4] (centre, width, depth, baseline).
  * Uses the plan's internal workspace, grown on demand (the first call for a
  * larger batch allocates).  The 7x7 median window replicates the first and
  * last frame of the batch at its edges, so results depend on how a stream is
  * cut into batches only within three frames of a cut.
  */
-cg_status cg_process_batch(cg_plan* plan, const int16_t* frames, int64_t n_frames,
+cg_status cg_process_batch(cg_plan* plan, const void* frames, int64_t n_frames,
                            float* out_params, void* stream);
 
 /*
@@ -154,7 +179,7 @@ cg_status cg_process_batch(cg_plan* plan, const int16_t* frames, int64_t n_frame
  * Errors: CG_ERR_WORKSPACE if workspace_bytes is too small; CG_ERR_STATE for
  * CG_FIT_WARM_MLP before cg_set_mlp; CG_ERR_INVALID_ARG for unknown flags.
  */
-cg_status cg_process_batch_ex(cg_plan* plan, const int16_t* frames, int64_t n_frames,
+cg_status cg_process_batch_ex(cg_plan* plan, const void* frames, int64_t n_frames,
                               float* out_params, int32_t* out_iters, int32_t* out_status,
                               float* out_chi2, float* out_teeth, float* out_y, uint32_t flags,
                               void* workspace, size_t workspace_bytes, void* stream);
@@ -183,7 +208,7 @@ cg_status cg_process_batch_ex(cg_plan* plan, const int16_t* frames, int64_t n_fr
  * them.
  */
 #define CG_STATIC_SCRATCH_BYTES (64u << 20)
-cg_status cg_process_batch_static(cg_plan* plan, const int16_t* frames, int64_t n_frames,
+cg_status cg_process_batch_static(cg_plan* plan, const void* frames, int64_t n_frames,
                                   float* out_params, int32_t* out_iters, int32_t* out_status,
                                   float* out_chi2, uint32_t flags, void* stream);
 
@@ -193,7 +218,7 @@ cg_status cg_process_batch_static(cg_plan* plan, const int16_t* frames, int64_t 
  * (CG_DFT_*).  frames device int16[n_frames][frame_len]; outputs device
  * float32[n_frames][n_teeth].
  */
-cg_status cg_teeth(cg_plan* plan, const int16_t* frames, int64_t n_frames, float* out_teeth,
+cg_status cg_teeth(cg_plan* plan, const void* frames, int64_t n_frames, float* out_teeth,
                    float* out_y, uint32_t flags, void* stream);
 
 /*
@@ -203,7 +228,7 @@ cg_status cg_teeth(cg_plan* plan, const int16_t* frames, int64_t n_frames, float
  * out_ref device float32[n_teeth].  The plan's own reference is not changed;
  * copy the result to the host and pass it to cg_set_reference to install it.
  */
-cg_status cg_reference_from_frames(cg_plan* plan, const int16_t* ref_frames, int64_t n,
+cg_status cg_reference_from_frames(cg_plan* plan, const void* ref_frames, int64_t n,
                                    float* out_ref, void* stream);
 
 /*
@@ -433,7 +458,7 @@ cg_status cg_pipeline_destroy(cg_pipeline* pipe);
  * host buffer).  CG_ERR_RING_FULL (counted as an
  * overflow) when every slot is queued, running or holding unread results. */
 cg_status cg_pipeline_acquire(cg_pipeline* pipe, int32_t stream, int32_t* slot,
-                              int16_t** frames);
+                              void** frames);
 /* Hand a written slot to the dispatcher: n_frames in 1..max_burst_frames,
  * seq the caller's sequence number for this stream (increasing). */
 cg_status cg_pipeline_publish(cg_pipeline* pipe, int32_t stream, int32_t slot, int32_t n_frames,
@@ -446,7 +471,7 @@ cg_status cg_pipeline_publish(cg_pipeline* pipe, int32_t stream, int32_t slot, i
  * dispatcher wait for the copy).  CG_ERR_RING_FULL as for
  * cg_pipeline_acquire.  out_slot (may be NULL) receives the slot taken, so
  * the caller can keep src alive until that slot is handed out again. */
-cg_status cg_pipeline_put(cg_pipeline* pipe, int32_t stream, const int16_t* src, int32_t n_frames,
+cg_status cg_pipeline_put(cg_pipeline* pipe, int32_t stream, const void* src, int32_t n_frames,
                           int64_t seq, int32_t* out_slot);
 /* Pop the next burst of `stream` in publish order (CG_PIPE_KEEP_RESULTS),
  * once it has completed: bursts that complete before an earlier burst of
@@ -478,7 +503,7 @@ cg_status cg_pipeline_stats(cg_pipeline* pipe, double* out, int32_t n_out);
  * wavefront (*chosen) and its time per batch (*best_ms, may be NULL).
  * Synchronises the device; allocates a parameter buffer for the timing.
  */
-cg_status cg_autotune(cg_plan* plan, const int16_t* frames, int64_t n_frames, uint32_t flags,
+cg_status cg_autotune(cg_plan* plan, const void* frames, int64_t n_frames, uint32_t flags,
                       void* workspace, size_t workspace_bytes, int32_t* chosen, float* best_ms);
 
 /* Static description of a status code. */

@@ -27,6 +27,8 @@ _pf32 = _c.POINTER(_c.c_float)
 # name -> (restype, argtypes); device pointers are passed as void*
 SIGNATURES = {
     "cg_create_plan": (_i32, [_i32, _dbl, _pi32, _i32, _pf32, _c.POINTER(_vp)]),
+    "cg_create_plan_ex": (_i32, [_i32, _dbl, _pi32, _i32, _pf32, _i32, _c.POINTER(_vp)]),
+    "cg_plan_sample_bytes": (_i32, [_vp, _pi32]),
     "cg_destroy_plan": (_i32, [_vp]),
     "cg_set_reference": (_i32, [_vp, _pf32]),
     "cg_plan_info": (_i32, [_vp, _pi32, _pi32, _c.POINTER(_dbl)]),

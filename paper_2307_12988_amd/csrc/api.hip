@@ -28,10 +28,17 @@ size_t ws_bytes(int64_t nf, int k) {
 
 bool is_pow2(int32_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-cg_status check_geometry(int32_t n, double fs, const int32_t* bins, int32_t k) {
+cg_status check_geometry(int32_t n, double fs, const int32_t* bins, int32_t k,
+                         int32_t sample_type) {
   if (!bins) return CG_ERR_NULL;
-  if (!is_pow2(n) || n < CG_MIN_FRAME_LEN || n > CG_MAX_FRAME_LEN) {
-    set_detail("frame_len must be a power of two in [512, 8192]");
+  if (sample_type != CG_SAMPLES_INT16 && sample_type != CG_SAMPLES_INT8) {
+    set_detail("sample_type must be CG_SAMPLES_INT16 or CG_SAMPLES_INT8");
+    return CG_ERR_INVALID_ARG;
+  }
+  const bool pow2 = is_pow2(n) && n >= CG_MIN_FRAME_LEN && n <= CG_MAX_FRAME_LEN;
+  if (n != CG_PAPER_FRAME_LEN && !(pow2 && sample_type == CG_SAMPLES_INT16)) {
+    set_detail("frame_len must be a power of two in [512, 8192] (int16 samples) or 2200 "
+               "(int8 or int16 samples)");
     return CG_ERR_UNSUPPORTED;
   }
   if (k < 1) {
@@ -111,6 +118,8 @@ void free_plan(cg_plan* p) {
   if (p->d_ref) (void)hipFree(p->d_ref);
   if (p->d_half_inv_ref) (void)hipFree(p->d_half_inv_ref);
   if (p->d_tw) (void)hipFree(p->d_tw);
+  if (p->d_tw_mixed) (void)hipFree(p->d_tw_mixed);
+  if (p->d_tooth_w) (void)hipFree(p->d_tooth_w);
   if (p->ws) (void)hipFree(p->ws);
   for (auto* b : p->d_mfma_bf)
     if (b) (void)hipFree(b);
@@ -157,10 +166,17 @@ const char* cg_version(void) { return "combgpu-mi355x 0.1.0 gfx950"; }
 
 cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins,
                          int32_t n_teeth, const float* ref_spectrum, cg_plan** out_plan) {
+  return cg_create_plan_ex(frame_len, fs, tooth_bins, n_teeth, ref_spectrum, CG_SAMPLES_INT16,
+                           out_plan);
+}
+
+cg_status cg_create_plan_ex(int32_t frame_len, double fs, const int32_t* tooth_bins,
+                            int32_t n_teeth, const float* ref_spectrum, int32_t sample_type,
+                            cg_plan** out_plan) {
   cg::set_detail("");
   if (!out_plan) return CG_ERR_NULL;
   *out_plan = nullptr;
-  cg_status st = cg::check_geometry(frame_len, fs, tooth_bins, n_teeth);
+  cg_status st = cg::check_geometry(frame_len, fs, tooth_bins, n_teeth, sample_type);
   if (st != CG_OK) return st;
   st = cg::check_ref(ref_spectrum, n_teeth);
   if (st != CG_OK) return st;
@@ -169,6 +185,7 @@ cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins
   if (!p) return CG_ERR_OOM;
   p->n = frame_len;
   p->m = frame_len / 2;
+  p->sample_bytes = sample_type == CG_SAMPLES_INT8 ? 1 : 2;
   p->k = n_teeth;
   p->fs = fs;
   p->h_bins.assign(tooth_bins, tooth_bins + n_teeth);
@@ -201,6 +218,28 @@ cg_status cg_create_plan(int32_t frame_len, double fs, const int32_t* tooth_bins
   CG_TRY(cg::upload_reference(p, ref_spectrum), "copy ref");
   CG_TRY(hipMemcpy(p->d_tw, tw.data(), sizeof(float2) * frame_len, hipMemcpyHostToDevice),
          "copy twiddles");
+  if (frame_len == CG_PAPER_FRAME_LEN) {
+    // mixed-radix tables: W_M^e of the 1100-point complex FFT and, per
+    // tooth, W_N^bin of the real-FFT untangling, built in FP64
+    const int32_t m = frame_len / 2;
+    std::vector<float2> twm(m), ttw(n_teeth);
+    for (int32_t e = 0; e < m; ++e) {
+      const double a = 2.0 * (double)e / (double)m;
+      twm[e].x = (float)std::cos(M_PI * a);
+      twm[e].y = (float)-std::sin(M_PI * a);
+    }
+    for (int32_t i = 0; i < n_teeth; ++i) {
+      const double a = 2.0 * (double)tooth_bins[i] / (double)frame_len;
+      ttw[i].x = (float)std::cos(M_PI * a);
+      ttw[i].y = (float)-std::sin(M_PI * a);
+    }
+    CG_TRY(hipMalloc(&p->d_tw_mixed, sizeof(float2) * m), "hipMalloc mixed twiddles");
+    CG_TRY(hipMalloc(&p->d_tooth_w, sizeof(float2) * n_teeth), "hipMalloc tooth twiddles");
+    CG_TRY(hipMemcpy(p->d_tw_mixed, twm.data(), sizeof(float2) * m, hipMemcpyHostToDevice),
+           "copy mixed twiddles");
+    CG_TRY(hipMemcpy(p->d_tooth_w, ttw.data(), sizeof(float2) * n_teeth, hipMemcpyHostToDevice),
+           "copy tooth twiddles");
+  }
   CG_TRY(cg::resolve_static_scratch(p->device), "fixed scratch: hipGetSymbolAddress");
 #undef CG_TRY
   p->fft_blocks = cg::fft_grid_limit(p);
@@ -221,6 +260,12 @@ cg_status cg_set_reference(cg_plan* p, const float* ref) {
   if (e == hipSuccess) e = cg::upload_reference(p, ref);
   if (e != hipSuccess) return hip_fail(e, "cg_set_reference");
   p->h_ref.assign(ref, ref + p->k);
+  return CG_OK;
+}
+
+cg_status cg_plan_sample_bytes(const cg_plan* p, int32_t* bytes) {
+  if (!p || !bytes) return CG_ERR_NULL;
+  *bytes = p->sample_bytes;
   return CG_OK;
 }
 
@@ -248,7 +293,7 @@ namespace {
 // given, else the fixed scratch array when no_alloc (no allocation of any
 // kind, matrix-core forms refused since they build their basis on first use),
 // else the plan's own, grown on demand.
-cg_status process_impl(cg_plan* p, const int16_t* frames, int64_t nf, float* out_params,
+cg_status process_impl(cg_plan* p, const void* frames, int64_t nf, float* out_params,
                        int32_t* out_iters, int32_t* out_status, float* out_chi2,
                        float* out_teeth, float* out_y, uint32_t flags, void* workspace,
                        size_t workspace_bytes, void* stream, bool no_alloc) {
@@ -268,6 +313,10 @@ cg_status process_impl(cg_plan* p, const int16_t* frames, int64_t nf, float* out
   if (!cg::aligned(frames, 4)) {
     cg::set_detail("frames must be 4-byte aligned");
     return CG_ERR_INVALID_ARG;
+  }
+  if (dft != CG_DFT_FFT && (p->sample_bytes != 2 || p->n == CG_PAPER_FRAME_LEN)) {
+    cg::set_detail("the matrix-core forms take int16 frames of a power-of-two length");
+    return CG_ERR_UNSUPPORTED;
   }
   if (dft != CG_DFT_FFT) {
     if (no_alloc) {
@@ -329,7 +378,8 @@ cg_status process_impl(cg_plan* p, const int16_t* frames, int64_t nf, float* out
   cur += cg::align256((size_t)nf * sizeof(float));
   int32_t* fb_count = reinterpret_cast<int32_t*>(cur);
   hipError_t e = dft == CG_DFT_FFT ? cg::launch_fft_teeth(p, frames, nf, out_teeth, y, s)
-                                   : cg::launch_mfma_teeth(p, dft, frames, nf, out_teeth, y, s);
+                                   : cg::launch_mfma_teeth(p, dft, static_cast<const int16_t*>(frames),
+                                                           nf, out_teeth, y, s);
   if (e != hipSuccess) return hip_fail(e, "tooth transform launch");
   if (fit == CG_FIT_NONE) return CG_OK;
   if (fit == CG_FIT_WARM_MLP) {
@@ -366,7 +416,7 @@ cg_status process_impl(cg_plan* p, const int16_t* frames, int64_t nf, float* out
 
 extern "C" {
 
-cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, float* out_params,
+cg_status cg_process_batch_ex(cg_plan* p, const void* frames, int64_t nf, float* out_params,
                               int32_t* out_iters, int32_t* out_status, float* out_chi2,
                               float* out_teeth, float* out_y, uint32_t flags, void* workspace,
                               size_t workspace_bytes, void* stream) {
@@ -374,20 +424,20 @@ cg_status cg_process_batch_ex(cg_plan* p, const int16_t* frames, int64_t nf, flo
                           out_y, flags, workspace, workspace_bytes, stream, false);
 }
 
-cg_status cg_process_batch_static(cg_plan* p, const int16_t* frames, int64_t nf,
+cg_status cg_process_batch_static(cg_plan* p, const void* frames, int64_t nf,
                                   float* out_params, int32_t* out_iters, int32_t* out_status,
                                   float* out_chi2, uint32_t flags, void* stream) {
   return cg::process_impl(p, frames, nf, out_params, out_iters, out_status, out_chi2, nullptr,
                           nullptr, flags, nullptr, 0, stream, true);
 }
 
-cg_status cg_process_batch(cg_plan* p, const int16_t* frames, int64_t nf, float* out_params,
+cg_status cg_process_batch(cg_plan* p, const void* frames, int64_t nf, float* out_params,
                            void* stream) {
   return cg_process_batch_ex(p, frames, nf, out_params, nullptr, nullptr, nullptr, nullptr,
                              nullptr, CG_DFT_FFT | CG_FIT_COLD, nullptr, 0, stream);
 }
 
-cg_status cg_teeth(cg_plan* p, const int16_t* frames, int64_t nf, float* out_teeth, float* out_y,
+cg_status cg_teeth(cg_plan* p, const void* frames, int64_t nf, float* out_teeth, float* out_y,
                    uint32_t flags, void* stream) {
   if (!p) return CG_ERR_NULL;
   if ((flags & ~CG_DFT_MASK) != 0u || flags > CG_DFT_MFMA_FP16X2) return CG_ERR_INVALID_ARG;
@@ -395,7 +445,7 @@ cg_status cg_teeth(cg_plan* p, const int16_t* frames, int64_t nf, float* out_tee
                              flags | CG_FIT_NONE, nullptr, 0, stream);
 }
 
-cg_status cg_reference_from_frames(cg_plan* p, const int16_t* ref_frames, int64_t n,
+cg_status cg_reference_from_frames(cg_plan* p, const void* ref_frames, int64_t n,
                                    float* out_ref, void* stream) {
   if (!p || !out_ref) return CG_ERR_NULL;
   if (n <= 0) return CG_ERR_INVALID_ARG;

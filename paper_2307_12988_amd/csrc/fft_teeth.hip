@@ -478,7 +478,7 @@ int max_blocks_t(const cg_plan* p) {
 }
 
 template <int LOGM, int TPT>
-hipError_t launch_tt(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
+hipError_t launch_tt(const cg_plan* p, const void* frames, int64_t nf, float* out_mag,
                      float* out_y, hipStream_t s, const int32_t* dev_n) {
   using S = FftShape<LOGM>;
   int64_t blocks = (nf + S::FPB - 1) / S::FPB;
@@ -494,7 +494,7 @@ hipError_t launch_tt(const cg_plan* p, const int16_t* frames, int64_t nf, float*
 }
 
 template <int LOGM>
-hipError_t launch_t(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
+hipError_t launch_t(const cg_plan* p, const void* frames, int64_t nf, float* out_mag,
                     float* out_y, hipStream_t s, const int32_t* dev_n) {
   switch (fft_teeth_per_thread<LOGM>(p->k)) {
     case 1: return launch_tt<LOGM, 1>(p, frames, nf, out_mag, out_y, s, dev_n);
@@ -507,6 +507,7 @@ hipError_t launch_t(const cg_plan* p, const int16_t* frames, int64_t nf, float* 
 }  // namespace
 
 int fft_grid_limit(const cg_plan* p) {
+  if (p->n == 2200) return fft_mixed_grid_limit(p);
   switch (p->m) {
     case 256: return max_blocks_t<8>(p);
     case 512: return max_blocks_t<9>(p);
@@ -517,8 +518,10 @@ int fft_grid_limit(const cg_plan* p) {
   }
 }
 
-hipError_t launch_fft_teeth(const cg_plan* p, const int16_t* frames, int64_t nf, float* out_mag,
+hipError_t launch_fft_teeth(const cg_plan* p, const void* frames, int64_t nf, float* out_mag,
                             float* out_y, hipStream_t s, const int32_t* dev_n) {
+  if (p->n == 2200) return launch_fft_mixed(p, frames, nf, out_mag, out_y, s, dev_n);
+  if (p->sample_bytes != 2) return hipErrorInvalidValue;
   switch (p->m) {
     case 256: return launch_t<8>(p, frames, nf, out_mag, out_y, s, dev_n);
     case 512: return launch_t<9>(p, frames, nf, out_mag, out_y, s, dev_n);

@@ -15,6 +15,7 @@ struct cg_mlp;  // learned warm-start weights (mlp.hip)
 
 struct cg_plan {
   int32_t n = 0;          // frame length (samples)
+  int32_t sample_bytes = 2;  // 2: int16 samples, 1: int8 samples
   int32_t m = 0;          // n / 2 : complex FFT length
   int32_t k = 0;          // number of teeth
   double fs = 0.0;        // sample rate (metadata)
@@ -23,6 +24,8 @@ struct cg_plan {
   float* d_ref = nullptr;      // [k] reference amplitudes
   float* d_half_inv_ref = nullptr;  // [k] 0.5 / reference (FFT epilogue)
   float2* d_tw = nullptr;      // [n] W_n^e = (cos 2 pi e/n, -sin 2 pi e/n), e = 0..n-1
+  float2* d_tw_mixed = nullptr;  // 2200-sample frames: [1100] W_1100^e
+  float2* d_tooth_w = nullptr;   // 2200-sample frames: [k] W_2200^bin per tooth
   std::vector<int32_t> h_bins;
   std::vector<float> h_ref;
   void* ws = nullptr;          // plan-owned workspace (grown on demand)
@@ -64,8 +67,14 @@ void set_detail(const std::string& s);
 // read by the kernels at run time (at most n_frames, the capacity the grid is
 // sized for), so one captured graph serves bursts of any size.
 // Blocks of the persistent FFT kernel that fit on the plan's device at once.
+// frames: n_frames x frame_len samples of the plan's sample type.
 int fft_grid_limit(const cg_plan* p);
-hipError_t launch_fft_teeth(const cg_plan* p, const int16_t* frames, int64_t n_frames,
+hipError_t launch_fft_teeth(const cg_plan* p, const void* frames, int64_t n_frames,
+                            float* out_mag, float* out_y, hipStream_t s,
+                            const int32_t* dev_n = nullptr);
+// The paper's 2200-sample frames (mixed-radix FFT, int8 or int16 samples).
+int fft_mixed_grid_limit(const cg_plan* p);
+hipError_t launch_fft_mixed(const cg_plan* p, const void* frames, int64_t n_frames,
                             float* out_mag, float* out_y, hipStream_t s,
                             const int32_t* dev_n = nullptr);
 

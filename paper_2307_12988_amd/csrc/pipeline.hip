@@ -81,8 +81,8 @@ struct Burst {
 };
 
 struct PipeSlot {
-  int16_t* frames = nullptr;
-  int16_t* h_frames = nullptr;  // pinned host frame buffer (host ring only)
+  void* frames = nullptr;       // device frame buffer (the plan's sample type)
+  void* h_frames = nullptr;     // pinned host frame buffer (host ring only)
   hipEvent_t copied = nullptr;  // host ring: the burst's copy has landed
   int32_t* n_dev = nullptr;
   int32_t* n_host = nullptr;  // pinned
@@ -265,11 +265,11 @@ void free_slot(PipeSlot& sl) {
 
 hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap, bool host_ring) {
   const cg_plan* p = ps.plan;
-  hipError_t e = hipMalloc(&sl.frames, (size_t)cap * p->n * sizeof(int16_t));
+  const size_t frame_bytes = (size_t)cap * p->n * p->sample_bytes;
+  hipError_t e = hipMalloc(&sl.frames, frame_bytes);
   if (e != hipSuccess) return e;
   if (host_ring) {
-    if ((e = hipHostMalloc(&sl.h_frames, (size_t)cap * p->n * sizeof(int16_t))) != hipSuccess)
-      return e;
+    if ((e = hipHostMalloc(&sl.h_frames, frame_bytes)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming)) != hipSuccess) return e;
   }
   // one device block for the count, spectra, start points and results
@@ -325,7 +325,7 @@ hipError_t launch_burst(cg_pipeline* P, const Burst& q) {
   hipStream_t lane = ps.lanes[ps.next_lane];
   ps.next_lane = (ps.next_lane + 1) % (int)ps.lanes.size();
   hipError_t e = hipSuccess;
-  const size_t bytes = (size_t)sl.n * ps.plan->n * sizeof(int16_t);
+  const size_t bytes = (size_t)sl.n * ps.plan->n * ps.plan->sample_bytes;
   if (P->host_ring) {
     // the host ring slot -> device on the copy stream (after a GPU-clock
     // stamp, the earliest point of the burst the GPU sees); the lane waits
@@ -367,7 +367,7 @@ void complete(cg_pipeline* P, const Burst& q, double t) {
   ps.frames += sl.n;
   P->bursts += 1;
   P->frames += sl.n;
-  P->bytes += (double)sl.n * (P->dry ? 0.0 : (double)ps.plan->n * 2.0);
+  P->bytes += (double)sl.n * (P->dry ? 0.0 : (double)ps.plan->n * ps.plan->sample_bytes);
   P->t_last = t;
   keep_sample(P->lat_ms, (t - sl.t_pub) * 1e3);
   if (P->dry) {
@@ -561,7 +561,7 @@ cg_status cg_pipeline_destroy(cg_pipeline* P) {
   return CG_OK;
 }
 
-cg_status cg_pipeline_acquire(cg_pipeline* P, int32_t stream, int32_t* slot, int16_t** frames) {
+cg_status cg_pipeline_acquire(cg_pipeline* P, int32_t stream, int32_t* slot, void** frames) {
   if (!P || !slot) return CG_ERR_NULL;
   if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lk(P->mu);
@@ -622,7 +622,7 @@ cg_status cg_pipeline_publish(cg_pipeline* P, int32_t stream, int32_t slot, int3
   return publish_burst(P, stream, slot, n_frames, seq, nullptr, 0);
 }
 
-cg_status cg_pipeline_put(cg_pipeline* P, int32_t stream, const int16_t* src, int32_t n_frames,
+cg_status cg_pipeline_put(cg_pipeline* P, int32_t stream, const void* src, int32_t n_frames,
                           int64_t seq, int32_t* out_slot) {
   if (out_slot) *out_slot = -1;
   if (!P || !src) return CG_ERR_NULL;
@@ -630,11 +630,12 @@ cg_status cg_pipeline_put(cg_pipeline* P, int32_t stream, const int16_t* src, in
   if (stream < 0 || stream >= (int32_t)P->st.size()) return CG_ERR_INVALID_ARG;
   if (n_frames < 1 || n_frames > P->cap) return CG_ERR_INVALID_ARG;
   int32_t slot = -1;
-  int16_t* dst = nullptr;
+  void* dst = nullptr;
   cg_status st = cg_pipeline_acquire(P, stream, &slot, &dst);
   if (st != CG_OK) return st;
   if (out_slot) *out_slot = slot;
-  const size_t bytes = (size_t)n_frames * P->st[stream].plan->n * sizeof(int16_t);
+  const cg_plan* pl = P->st[stream].plan;
+  const size_t bytes = (size_t)n_frames * pl->n * pl->sample_bytes;
   if (P->host_ring) {
     // the host ring slot is written here (src must then be host memory); the
     // dispatcher copies it to the device
@@ -736,7 +737,7 @@ cg_status cg_pipeline_stats(cg_pipeline* P, double* out, int32_t n_out) {
   return CG_OK;
 }
 
-cg_status cg_autotune(cg_plan* p, const int16_t* frames, int64_t nf, uint32_t flags,
+cg_status cg_autotune(cg_plan* p, const void* frames, int64_t nf, uint32_t flags,
                       void* workspace, size_t workspace_bytes, int32_t* chosen, float* best_ms) {
   if (!p || !frames || !chosen) return CG_ERR_NULL;
   if (nf < 1) return CG_ERR_INVALID_ARG;

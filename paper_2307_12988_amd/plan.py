@@ -50,20 +50,32 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-class Plan:
-    """Plan for frames of `frame_len` int16 samples and `len(tooth_bins)` teeth."""
+SAMPLES_INT16, SAMPLES_INT8 = 0, 1
 
-    def __init__(self, frame_len: int, fs: float, tooth_bins, ref_spectrum):
+
+class Plan:
+    """Plan for frames of `frame_len` samples (int16, or int8 with
+    sample_type="int8") and `len(tooth_bins)` teeth."""
+
+    def __init__(self, frame_len: int, fs: float, tooth_bins, ref_spectrum,
+                 sample_type: str = "int16"):
         self._lib = _lib.load()
         bins = np.ascontiguousarray(np.asarray(tooth_bins), dtype=np.int32)
         ref = np.ascontiguousarray(np.asarray(ref_spectrum), dtype=np.float32)
         if bins.ndim != 1 or ref.shape != bins.shape:
             raise ValueError("tooth_bins and ref_spectrum must be 1-D of equal length")
+        if sample_type not in ("int16", "int8"):
+            raise ValueError("sample_type must be 'int16' or 'int8'")
         handle = ctypes.c_void_p()
-        st = self._lib.cg_create_plan(int(frame_len), float(fs),
-                                      bins.ctypes.data_as(_lib._pi32), int(bins.shape[0]),
-                                      ref.ctypes.data_as(_lib._pf32), ctypes.byref(handle))
-        _lib.check(st, "cg_create_plan")
+        st = self._lib.cg_create_plan_ex(int(frame_len), float(fs),
+                                         bins.ctypes.data_as(_lib._pi32), int(bins.shape[0]),
+                                         ref.ctypes.data_as(_lib._pf32),
+                                         SAMPLES_INT8 if sample_type == "int8" else SAMPLES_INT16,
+                                         ctypes.byref(handle))
+        _lib.check(st, "cg_create_plan_ex")
+        self.sample_type = sample_type
+        self.sample_dtype = torch.int8 if sample_type == "int8" else torch.int16
+        self.np_dtype = np.int8 if sample_type == "int8" else np.int16
         self._h = handle
         self.frame_len = int(frame_len)
         self.fs = float(fs)
@@ -116,7 +128,7 @@ class Plan:
         if frames.dim() != 2 or frames.shape[1] != self.frame_len:
             raise ValueError(f"frames must be [n, {self.frame_len}]")
         nf = int(frames.shape[0])
-        return nf, _dev_ptr(frames, torch.int16, (nf, self.frame_len), "frames")
+        return nf, _dev_ptr(frames, self.sample_dtype, (nf, self.frame_len), "frames")
 
     def process(self, frames, params=None, iters=None, status=None, chi2=None, teeth=None,
                 y=None, flags: int = 0, workspace=None, want=("params",)):
@@ -462,6 +474,7 @@ class Pipeline:
                                              ctypes.byref(h))
         _lib.check(st, "cg_pipeline_create_ex")
         self.frame_len = [p.frame_len for p in plans] if plans is not None else None
+        self.np_dtype = [p.np_dtype for p in plans] if plans is not None else None
         self._h = h
         self.n_streams = ns
         self.max_burst = int(max_burst_frames)
@@ -493,14 +506,16 @@ class Pipeline:
         return slot.value, ptr.value
 
     def acquire_host(self, stream: int):
-        """Host ring: (slot, numpy int16 view [max_burst_frames, frame_len] of
-        the slot's pinned host buffer) or raises RingFull."""
+        """Host ring: (slot, numpy view [max_burst_frames, frame_len] of the
+        slot's pinned host buffer, in the plan's sample type) or raises
+        RingFull."""
         if not self.host_ring:
             raise ValueError("acquire_host needs a pipeline created with host_ring=True")
         slot, ptr = self.acquire(stream)
-        n = self.max_burst * self.frame_len[int(stream)]
-        buf = (ctypes.c_int16 * n).from_address(ptr)
-        return slot, np.frombuffer(buf, dtype=np.int16).reshape(self.max_burst, -1)
+        dt = np.dtype(self.np_dtype[int(stream)])
+        n = self.max_burst * self.frame_len[int(stream)] * dt.itemsize
+        buf = (ctypes.c_uint8 * n).from_address(ptr)
+        return slot, np.frombuffer(buf, dtype=dt).reshape(self.max_burst, -1)
 
     def publish(self, stream: int, slot: int, n_frames: int, seq: int):
         _lib.check(self._lib.cg_pipeline_publish(self._h, int(stream), int(slot), int(n_frames),
@@ -511,16 +526,21 @@ class Pipeline:
         [n, frame_len], contiguous; with the host ring a host numpy array or
         CPU tensor, copied into the ring on this thread) into a free slot and
         publish it.  Raises RingFull when the stream has no free slot."""
+        s = int(stream)
+        want_np = np.dtype(self.np_dtype[s]) if self.np_dtype else np.dtype(np.int16)
+        want_t = torch.int8 if want_np == np.int8 else torch.int16
         if isinstance(frames, np.ndarray):
             if not self.host_ring:
                 raise ValueError("numpy sources need a host-ring pipeline")
-            if frames.dtype != np.int16 or frames.ndim != 2 or not frames.flags.c_contiguous:
-                raise ValueError("frames must be a C-contiguous int16 array [n, frame_len]")
+            if frames.dtype != want_np or frames.ndim != 2 or not frames.flags.c_contiguous \
+                    or frames.shape[1] != self.frame_len[s]:
+                raise ValueError(f"frames must be a C-contiguous {want_np} array [n, frame_len]")
             ptr, nfr = frames.ctypes.data, int(frames.shape[0])
         else:
-            if not isinstance(frames, torch.Tensor) or frames.dtype != torch.int16 or \
-                    frames.dim() != 2 or not frames.is_contiguous():
-                raise ValueError("frames must be a contiguous int16 torch tensor [n, frame_len]")
+            if not isinstance(frames, torch.Tensor) or frames.dtype != want_t or \
+                    frames.dim() != 2 or not frames.is_contiguous() or \
+                    frames.shape[1] != self.frame_len[s]:
+                raise ValueError(f"frames must be a contiguous {want_t} tensor [n, frame_len]")
             if self.host_ring and frames.is_cuda:
                 raise ValueError("a host-ring pipeline takes host frames")
             ptr, nfr = frames.data_ptr(), int(frames.shape[0])

@@ -38,7 +38,7 @@ void run(bool keep, int n_streams, int slots, int bursts_per_stream, double us_p
     th.emplace_back([&, s] {
       for (int b = 0; b < bursts_per_stream; ++b) {
         int32_t slot = -1;
-        int16_t* buf = nullptr;
+        void* buf = nullptr;
         for (;;) {
           const cg_status a = cg_pipeline_acquire(pipe, s, &slot, &buf);
           if (a == CG_OK) break;
