@@ -15,6 +15,7 @@ initializer  7x7 median filter over the (frame, tooth) image and the start point
 lm           Levenberg-Marquardt fit of the Lorentzian cavity dip
 fano         projected Levenberg-Marquardt fit of the asymmetric Fano dip
 mlp          FP64 forward/backward of the warm-start network
+psd          displacement power spectral density and the mechanical resonance fit
 pipeline     the steps above chained for a batch of frames
 
 Every function names the passage it follows.  Where the paper is silent the

@@ -15,6 +15,7 @@ from .comb import (
     tooth_bins_paper_2200,
     make_batch,
     make_lorentzian_spectra,
+    make_displacement,
     spec_tiny,
     spec_paper_rate,
     spec_precision,
@@ -32,6 +33,7 @@ __all__ = [
     "tooth_bins_paper_2200",
     "make_batch",
     "make_lorentzian_spectra",
+    "make_displacement",
     "spec_tiny",
     "spec_paper_rate",
     "spec_precision",

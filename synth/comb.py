@@ -341,3 +341,32 @@ def spec_multistream(seed: int = 100, n_streams: int = 16) -> Sequence[StreamSpe
                               bins=tooth_bins_interleaved(n, k), f_mech=fm,
                               width=(w, w), depth=(d, d), snr_db=(snr, snr)))
     return out
+
+
+def make_displacement(n: int, fs: float, f0: float, q: float, drive: float, floor: float,
+                      drift: float, seed: int, chunk: int = 1 << 22) -> np.ndarray:
+    """A displacement series (teeth) as the fitted centres of a still
+    accelerometer would give it: the thermomechanical resonance (a damped
+    oscillator driven by white force noise, integrated exactly at the frame
+    rate as the second-order recursion x[t] = a1 x[t-1] + a2 x[t-2] + e[t],
+    poles r e^{+-i theta}, r = exp(-pi f0 / (Q fs)), theta = 2 pi f0
+    sqrt(1 - 1/(4 Q^2)) / fs, e white with deviation `drive`), a white
+    measurement floor of deviation `floor` (the centre fit's noise) and a slow
+    random-walk drift of step deviation `drift` (thermal and humidity
+    drifts).  float32 [n]."""
+    from scipy.signal import lfilter
+    rng = np.random.default_rng([int(seed), 11])
+    r = np.exp(-np.pi * f0 / (q * fs))
+    theta = 2.0 * np.pi * f0 * np.sqrt(1.0 - 1.0 / (4.0 * q * q)) / fs
+    a1, a2 = 2.0 * r * np.cos(theta), -r * r
+    out = np.empty(n, dtype=np.float32)
+    zi = np.zeros(2)
+    walk = 0.0
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        e = drive * rng.standard_normal(b - a)
+        x, zi = lfilter([1.0], [1.0, -a1, -a2], e, zi=zi)
+        steps = np.cumsum(drift * rng.standard_normal(b - a)) + walk
+        walk = float(steps[-1])
+        out[a:b] = x + steps + floor * rng.standard_normal(b - a)
+    return out
