@@ -667,6 +667,86 @@ def host_ingest(args, torch, cg, dev):
     plan.close()
 
 
+def psd_workload(args, torch, cg, dev):
+    """Displacement PSD and mechanical resonance fit at the paper's frame rate
+    (1 MHz: one fitted centre per 1 us frame): a displacement series with the
+    thermomechanical resonance (f0 = 23.7 kHz, Q = 115), a white fit-noise
+    floor and a slow drift, Welch with 2^16-sample segments, the band
+    15-35 kHz, the oscillator fit; averaging windows of 1 s, 10 s and
+    10 min (--seconds caps the longest).  Per window: the PSD kernels' time
+    and throughput, the fit's f0 and Q, and the FP64 oracle on the 1 s
+    window (PSD and fit)."""
+    from oracle import psd as opsd
+    fs, f0, q = 1.0e6, 23.7e3, 115.0
+    seg = 1 << 16
+    k_lo, nb = cg.psd_band(seg, fs, 15e3, 35e3)
+    df = fs / seg
+    windows = [w for w in (1.0, 10.0, 600.0) if w <= max(args.seconds, 1.0)]
+    n_max = int(fs * windows[-1])
+    _log(f"generating {n_max} displacement samples ...")
+    t0 = time.perf_counter()
+    xs = torch.empty(n_max, dtype=torch.float32, device=dev)
+    chunk = 1 << 24
+    pos = 0
+    host_first = None
+    for c in range(0, n_max, chunk):
+        part = synth.make_displacement(min(chunk, n_max - c), fs, f0, q, drive=1e-3, floor=1e-2,
+                                       drift=1e-6, seed=1000 + c // chunk)
+        if host_first is None:
+            host_first = part[:int(fs)].copy()
+        xs[pos:pos + part.shape[0]] = torch.from_numpy(part).to(dev)
+        pos += part.shape[0]
+    _log(f"  {time.perf_counter() - t0:.1f} s")
+    rows = []
+    for w in windows:
+        n = int(fs * w)
+        series = xs[:n]
+        out = cg.psd_welch(series, fs, seg, k_lo, nb)      # warm-up (and workspace)
+        torch.cuda.synchronize(dev)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        reps = 3 if w <= 10 else 1
+        stream = torch.cuda.current_stream(dev)
+        ev[0].record(stream)
+        for _ in range(reps):
+            out = cg.psd_welch(series, fs, seg, k_lo, nb)
+        ev[1].record(stream)
+        torch.cuda.synchronize(dev)
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        fit = cg.resonance_fit(out, k_lo * df, df).cpu().numpy()
+        n_seg = (n - seg) // (seg // 2) + 1
+        alg_bytes = n_seg * seg * 4.0          # each segment's samples read once
+        rows.append({"window_s": w, "samples": n, "segments": int(n_seg), "psd_ms": ms,
+                     "samples_per_s": n / (ms * 1e-3),
+                     "GBps_series": alg_bytes / (ms * 1e-3) / 1e9,
+                     "frac_of_hbm_peak": alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "f0_Hz": float(fit[1]), "Q": float(fit[2]), "fit_iters": int(fit[5]),
+                     "fit_status": int(fit[6]),
+                     "realtime_factor": w / (ms * 1e-3)})
+    line = {"metric": METRIC, "value": rows[-1]["GBps_series"], "unit": "GB/s", "n_gpus": 1,
+            "steps": 1, "warmup": 1, "ms_per_step": rows[-1]["psd_ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"displacement PSD (Welch, 2^16-sample segments, half overlap, "
+                                   f"Hann) of a 1 MHz centre series and the resonance fit over "
+                                   f"15-35 kHz; windows {windows} s",
+                       "seg_len": seg, "band_bins": nb},
+            "windows": rows}
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        o_psd = opsd.welch_band(host_first.astype(np.float64), fs, seg, k_lo, nb)
+        f = (k_lo + np.arange(nb)) * df
+        p, it, st, _ = opsd.oscillator_fit(f, o_psd)
+        dt = time.perf_counter() - t0
+        g1 = cg.psd_welch(xs[:int(fs)], fs, seg, k_lo, nb).cpu().numpy()
+        line["cpu_baseline"] = {"value": int(fs) * 4 / dt / 1e9, "unit": "GB/s",
+                                "cores": None, "kind": "oracle",
+                                "sample": f"the 1 s window: FP64 Welch at the band bins and the "
+                                          f"fit, {dt:.1f} s", "host": host_info()}
+        line["parity_1s"] = {"psd_max_rel_err": float(np.max(np.abs(g1 - o_psd) / o_psd)),
+                             "f0_oracle": float(p[1]), "Q_oracle": float(p[2]),
+                             "f0_gpu": rows[0]["f0_Hz"], "Q_gpu": rows[0]["Q"]}
+    print(json.dumps(line), flush=True)
+
+
 def multistream_parity(args, torch, cg, dev, specs, plans, pools, gen, w, tune):
     """Accuracy leg of the multi-stream workload: two bursts per stream
     through a pipeline that keeps its results, and a fixed 1-in-64 frame
@@ -890,7 +970,7 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["paper_rate", "tiny", "precision", "multistream",
-                                           "warm", "fano", "paper8", "host_ingest"],
+                                           "warm", "fano", "paper8", "host_ingest", "psd"],
                     default="paper_rate",
                     help="paper_rate: the headline line; precision: 131072 x 4096 frames, one "
                          "line per tooth-DFT form (FFT and the three matrix-core forms); "
@@ -943,6 +1023,8 @@ def main():
         return fano_workload(args, torch, cg, dev)
     if args.workload == "host_ingest":
         return host_ingest(args, torch, cg, dev)
+    if args.workload == "psd":
+        return psd_workload(args, torch, cg, dev)
     spec = synth.spec_paper_rate()
     if args.workload == "tiny":
         # the small plain workload (4096 x 1024-sample frames, 100 teeth)

@@ -506,6 +506,47 @@ cg_status cg_pipeline_stats(cg_pipeline* pipe, double* out, int32_t n_out);
 cg_status cg_autotune(cg_plan* plan, const void* frames, int64_t n_frames, uint32_t flags,
                       void* workspace, size_t workspace_bytes, int32_t* chosen, float* best_ms);
 
+/*
+ * Displacement power spectral density and the mechanical resonance fit
+ * (paper, Experimental Results and the figure of the power spectral density:
+ * the fitted centres form a displacement series; its PSD averaged over 1 s,
+ * 10 s and 10 min shows the thermomechanical resonance near 24 kHz, whose fit
+ * gives the resonance frequency f and quality factor Q).
+ *
+ * cg_psd_band: the bins k_lo .. k_lo + n_bins - 1 of segments of seg_len
+ * samples that cover [f_lo, f_hi] Hz at sample rate fs (bin k is k fs /
+ * seg_len Hz; clipped at seg_len / 2).
+ * cg_psd_welch: Welch's averaged periodogram of `series` (device float32
+ * [n], e.g. the centres of consecutive frames, fs = frame rate): segments of
+ * seg_len (16384, 32768, 65536 or 131072) samples overlapping by half,
+ * segment mean removed, periodic Hann window, one-sided density (units^2 /
+ * Hz; factor 1 instead of 2 at DC and Nyquist), averaged over the segments;
+ * out_psd device float64 [n_bins] for the band bins.  FP32 transforms (the
+ * half-length complex FFT of even/odd-packed samples, split 128-point
+ * columns x rows), FP64 averages.  Needs n >= seg_len, an 8-byte aligned
+ * series and a 256-byte aligned device workspace of
+ * cg_psd_workspace_bytes() bytes (segments are processed in chunks of up to
+ * CG_PSD_CHUNK).
+ * cg_resonance_fit: fits S(f) = A / ((f0^2 - f^2)^2 + (f0 f / Q)^2) + B to
+ * a band of the PSD (device float64 [n_bins], n_bins 8..CG_PSD_MAX_FIT_BINS,
+ * bin b at f_first + b df Hz) by Levenberg-Marquardt on ln S in FP64 (lam0
+ * 1e-3, /10 on accept, *10 on reject, converged when an accepted step lowers
+ * chi2 by at most tol chi2; at most max_iter iterations), starting from the
+ * peak bin, the half-width of the peak above the floor (the median of the
+ * band's lowest quarter) and the peak height.  out: device float64 [7] =
+ * ln A, f0 (Hz), Q, ln B, chi2, iterations, status (CG_FIT_*).
+ */
+#define CG_PSD_CHUNK 1024
+#define CG_PSD_MAX_FIT_BINS 2048
+cg_status cg_psd_band(int32_t seg_len, double fs, double f_lo, double f_hi, int32_t* k_lo,
+                      int32_t* n_bins);
+cg_status cg_psd_workspace_bytes(int64_t n, int32_t seg_len, int32_t n_bins, size_t* bytes);
+cg_status cg_psd_welch(const float* series, int64_t n, double fs, int32_t seg_len, int32_t k_lo,
+                       int32_t n_bins, double* out_psd, void* workspace, size_t workspace_bytes,
+                       void* stream);
+cg_status cg_resonance_fit(const double* psd, int32_t n_bins, double f_first, double df,
+                           int32_t max_iter, double tol, double* out, void* stream);
+
 /* Static description of a status code. */
 const char* cg_status_string(cg_status status);
 

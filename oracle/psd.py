@@ -22,7 +22,11 @@ Readings (the paper names neither the estimator nor the fitted model):
   relative), parameters p = (ln A, f0, Q, ln B), by Levenberg-Marquardt with
   the plain fit's schedule (lam0 = 1e-3, /10 on accept, *10 on reject,
   Cholesky), at most `max_iter` iterations, converged when an accepted step
-  lowers chi2 by at most tol * chi2;
+  lowers chi2 by at most tol * chi2, tol = 1e-9 by default (a tighter one
+  drives the damping so low on a measured spectrum that the normal matrix of
+  the four strongly correlated parameters stops being numerically positive
+  definite, after the parameters have settled far below their statistical
+  uncertainty);
 * start point: f0 at the largest band value; B the median of the band's
   lowest quarter of values; Q = f0 / (the width between the first bins on
   each side of the peak whose excess over B falls to half the peak's), at
@@ -107,7 +111,7 @@ def start_point(freqs, psd):
     return np.array([np.log(a), f0, q, np.log(max(b, 1e-300))])
 
 
-def oscillator_fit(freqs, psd, p0=None, max_iter: int = 100, tol: float = 1e-12,
+def oscillator_fit(freqs, psd, p0=None, max_iter: int = 100, tol: float = 1e-9,
                    lam0: float = 1e-3):
     """Returns (p = (ln A, f0, Q, ln B), iterations, status, chi2)."""
     f = np.asarray(freqs, dtype=np.float64)

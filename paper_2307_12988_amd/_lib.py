@@ -68,6 +68,10 @@ SIGNATURES = {
     "cg_pipeline_drain": (_i32, [_vp, _i32]),
     "cg_pipeline_stats": (_i32, [_vp, _c.POINTER(_dbl), _i32]),
     "cg_autotune": (_i32, [_vp, _vp, _i64, _u32, _vp, _sz, _pi32, _pf32]),
+    "cg_psd_band": (_i32, [_i32, _dbl, _dbl, _dbl, _pi32, _pi32]),
+    "cg_psd_workspace_bytes": (_i32, [_i64, _i32, _i32, _c.POINTER(_sz)]),
+    "cg_psd_welch": (_i32, [_vp, _i64, _dbl, _i32, _i32, _i32, _vp, _vp, _sz, _vp]),
+    "cg_resonance_fit": (_i32, [_vp, _i32, _dbl, _dbl, _i32, _dbl, _vp, _vp]),
     "cg_status_string": (_c.c_char_p, [_i32]),
     "cg_last_error_detail": (_c.c_char_p, []),
     "cg_version": (_c.c_char_p, []),

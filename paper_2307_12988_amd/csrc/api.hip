@@ -558,6 +558,73 @@ cg_status cg_fit_fano(cg_plan* p, const float* y, const float* p0, int64_t nf, i
   return CG_OK;
 }
 
+namespace {
+bool psd_len_ok(int32_t seg_len) {
+  return seg_len == 16384 || seg_len == 32768 || seg_len == 65536 || seg_len == 131072;
+}
+int64_t psd_segments(int64_t n, int32_t seg_len) {
+  return n < seg_len ? 0 : (n - seg_len) / (seg_len / 2) + 1;
+}
+int64_t psd_chunk(int64_t n_seg) { return n_seg < CG_PSD_CHUNK ? n_seg : CG_PSD_CHUNK; }
+}  // namespace
+
+cg_status cg_psd_band(int32_t seg_len, double fs, double f_lo, double f_hi, int32_t* k_lo,
+                      int32_t* n_bins) {
+  if (!k_lo || !n_bins) return CG_ERR_NULL;
+  if (!psd_len_ok(seg_len) || !(fs > 0.0) || !std::isfinite(fs) || !std::isfinite(f_lo) ||
+      !std::isfinite(f_hi) || !(f_lo >= 0.0) || !(f_hi >= f_lo))
+    return CG_ERR_INVALID_ARG;
+  const double bin = fs / (double)seg_len;
+  int64_t lo = (int64_t)std::ceil(f_lo / bin), hi = (int64_t)std::floor(f_hi / bin);
+  if (hi > seg_len / 2) hi = seg_len / 2;
+  if (hi < lo) return CG_ERR_INVALID_ARG;
+  *k_lo = (int32_t)lo;
+  *n_bins = (int32_t)(hi - lo + 1);
+  return CG_OK;
+}
+
+cg_status cg_psd_workspace_bytes(int64_t n, int32_t seg_len, int32_t n_bins, size_t* bytes) {
+  if (!bytes) return CG_ERR_NULL;
+  if (!psd_len_ok(seg_len) || n_bins < 1 || n < seg_len) return CG_ERR_INVALID_ARG;
+  *bytes = cg::psd_workspace_bytes(psd_chunk(psd_segments(n, seg_len)), seg_len, n_bins);
+  return CG_OK;
+}
+
+cg_status cg_psd_welch(const float* series, int64_t n, double fs, int32_t seg_len, int32_t k_lo,
+                       int32_t n_bins, double* out_psd, void* workspace, size_t workspace_bytes,
+                       void* stream) {
+  cg::set_detail("");
+  if (!series || !out_psd || !workspace) return CG_ERR_NULL;
+  if (!psd_len_ok(seg_len) || n < seg_len || !(fs > 0.0) || !std::isfinite(fs) || k_lo < 0 ||
+      n_bins < 1 || k_lo + n_bins - 1 > seg_len / 2) {
+    cg::set_detail("seg_len in {2^14..2^17}, n >= seg_len, band inside [0, seg_len/2]");
+    return CG_ERR_INVALID_ARG;
+  }
+  if (!cg::aligned(series, 8) || !cg::aligned(workspace, 256)) {
+    cg::set_detail("series must be 8-byte and workspace 256-byte aligned");
+    return CG_ERR_INVALID_ARG;
+  }
+  const int64_t chunk = psd_chunk(psd_segments(n, seg_len));
+  if (workspace_bytes < cg::psd_workspace_bytes(chunk, seg_len, n_bins)) return CG_ERR_WORKSPACE;
+  hipError_t e = cg::launch_psd(series, n, fs, seg_len, k_lo, n_bins, out_psd, workspace, chunk,
+                                reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "psd launch");
+  return CG_OK;
+}
+
+cg_status cg_resonance_fit(const double* psd, int32_t n_bins, double f_first, double df,
+                           int32_t max_iter, double tol, double* out, void* stream) {
+  if (!psd || !out) return CG_ERR_NULL;
+  if (n_bins < 8 || n_bins > CG_PSD_MAX_FIT_BINS || !(df > 0.0) || !std::isfinite(df) ||
+      !std::isfinite(f_first) || !(f_first >= 0.0) || max_iter < 1 || max_iter > 10000 ||
+      !(tol >= 0.0))
+    return CG_ERR_INVALID_ARG;
+  hipError_t e = cg::launch_osc_fit(psd, n_bins, f_first, df, max_iter, tol, out,
+                                    reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "resonance fit launch");
+  return CG_OK;
+}
+
 cg_status cg_set_mlp(cg_plan* p, const float* params, const float* out_mean, const float* out_std,
                      float noise_floor) {
   if (!p || !params || !out_mean || !out_std) return CG_ERR_NULL;

@@ -128,4 +128,11 @@ hipError_t launch_fallback_select(const float* chi2, int64_t n_frames, int k, fl
                                   int32_t* flags, int32_t* idx, int32_t* count, hipStream_t s,
                                   const int32_t* dev_n = nullptr);
 
+// Displacement PSD (Welch, band of bins) and the resonance fit (psd.hip).
+size_t psd_workspace_bytes(int64_t chunk_segments, int seg_len, int n_bins);
+hipError_t launch_psd(const float* x, int64_t n, double fs, int seg_len, int k_lo, int n_bins,
+                      double* out, void* ws, int64_t chunk_segments, hipStream_t s);
+hipError_t launch_osc_fit(const double* psd, int n_bins, double f_first, double df,
+                          int max_iter, double tol, double* out, hipStream_t s);
+
 }  // namespace cg

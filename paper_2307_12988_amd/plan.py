@@ -576,3 +576,49 @@ class Pipeline:
         _lib.check(self._lib.cg_pipeline_stats(self._h, out, len(STATS_FIELDS)),
                    "cg_pipeline_stats")
         return dict(zip(STATS_FIELDS, list(out)))
+
+
+def psd_band(seg_len: int, fs: float, f_lo: float, f_hi: float):
+    """(k_lo, n_bins) of the band [f_lo, f_hi] Hz for segments of seg_len."""
+    lib = _lib.load()
+    k_lo, nb = ctypes.c_int32(), ctypes.c_int32()
+    _lib.check(lib.cg_psd_band(int(seg_len), float(fs), float(f_lo), float(f_hi),
+                               ctypes.byref(k_lo), ctypes.byref(nb)), "cg_psd_band")
+    return k_lo.value, nb.value
+
+
+def psd_welch(series, fs: float, seg_len: int, k_lo: int, n_bins: int, workspace=None):
+    """Welch density of a device float32 series at bins k_lo .. k_lo+n_bins-1
+    (device float64 tensor), see cg_psd_welch."""
+    lib = _lib.load()
+    if not isinstance(series, torch.Tensor) or not series.is_cuda or series.dtype != torch.float32 \
+            or series.dim() != 1 or not series.is_contiguous():
+        raise ValueError("series must be a contiguous 1-D float32 tensor on the GPU")
+    n = int(series.shape[0])
+    need = ctypes.c_size_t()
+    _lib.check(lib.cg_psd_workspace_bytes(n, int(seg_len), int(n_bins), ctypes.byref(need)),
+               "cg_psd_workspace_bytes")
+    if workspace is None:
+        workspace = torch.empty(need.value, dtype=torch.uint8, device=series.device)
+    out = torch.empty(int(n_bins), dtype=torch.float64, device=series.device)
+    st = lib.cg_psd_welch(ctypes.c_void_p(series.data_ptr()), n, float(fs), int(seg_len),
+                          int(k_lo), int(n_bins), ctypes.c_void_p(out.data_ptr()),
+                          ctypes.c_void_p(workspace.data_ptr()), int(workspace.numel()),
+                          _stream(series.device))
+    _lib.check(st, "cg_psd_welch")
+    return out
+
+
+def resonance_fit(psd, f_first: float, df: float, max_iter: int = 100, tol: float = 1e-9):
+    """Fit of the mechanical resonance to a device float64 PSD band: device
+    float64 [7] = ln A, f0, Q, ln B, chi2, iterations, status."""
+    lib = _lib.load()
+    if not isinstance(psd, torch.Tensor) or not psd.is_cuda or psd.dtype != torch.float64 \
+            or psd.dim() != 1 or not psd.is_contiguous():
+        raise ValueError("psd must be a contiguous 1-D float64 tensor on the GPU")
+    out = torch.empty(7, dtype=torch.float64, device=psd.device)
+    st = lib.cg_resonance_fit(ctypes.c_void_p(psd.data_ptr()), int(psd.shape[0]), float(f_first),
+                              float(df), int(max_iter), float(tol),
+                              ctypes.c_void_p(out.data_ptr()), _stream(psd.device))
+    _lib.check(st, "cg_resonance_fit")
+    return out

@@ -164,7 +164,7 @@ def _uniform(rng: np.random.Generator, rng_pair, size: int) -> np.ndarray:
 
 
 def make_batch(spec: StreamSpec, n_frames: int, seed: int, batch_index: int = 0,
-               chunk: int = 4096, noise: bool = True) -> Batch:
+               chunk: int = 4096, noise: bool = True, centre=None) -> Batch:
     """Generate `n_frames` consecutive frames of a stream.
 
     Batch b of a stream starts at frame b * n_frames, so consecutive batch
@@ -175,6 +175,7 @@ def make_batch(spec: StreamSpec, n_frames: int, seed: int, batch_index: int = 0,
     bins = np.asarray(spec.bins, dtype=np.int64)
     if bins.min() <= 0 or bins.max() >= n // 2:
         raise ValueError("tooth bins must lie strictly between DC and Nyquist")
+    given = None if centre is None else np.asarray(centre, dtype=np.float64)
     rng = np.random.default_rng([int(seed), int(batch_index)])
     first = int(batch_index) * int(n_frames)
     f_idx = first + np.arange(n_frames, dtype=np.float64)
@@ -204,6 +205,11 @@ def make_batch(spec: StreamSpec, n_frames: int, seed: int, batch_index: int = 0,
         tilt = sweep(spec.tilt[0], spec.tilt[1], 10.0, 200.0)
     else:
         raise ValueError(spec.centre_mode)
+    if given is not None:
+        # a given displacement series (teeth) in place of the spec's motion
+        if given.shape != (n_frames,):
+            raise ValueError("centre must hold one value per frame")
+        centre = given
     baseline = np.full(n_frames, float(spec.baseline))
     if spec.power_drift:
         phase = rng.uniform(0.0, 2.0 * np.pi)
