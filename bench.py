@@ -143,6 +143,15 @@ def mixed_peak_tflops(f32, f64):
     return (f32 + f64) / (f32 / VALU_FP32_PEAK_TFLOPS + f64 / VALU_FP64_PEAK_TFLOPS)
 
 
+def blas_threads():
+    """Threads the oracle's BLAS products run on (its other loops use one)."""
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+    except Exception:  # pragma: no cover
+        return 1
+
+
 def cpu_baseline(spec, frames, gpu_params, ref_frames, n_sample):
     """Time the FP64 oracle on a contiguous slice of the first batch and
     compare its centres with the GPU's for the same frames.  The stages are
@@ -150,11 +159,7 @@ def cpu_baseline(spec, frames, gpu_params, ref_frames, n_sample):
     threads), the 7x7 median, start points and the per-frame LM loop run on
     one Python thread."""
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = 1
+    threads = blas_threads()
     sl = frames[:n_sample]
     t0 = time.perf_counter()
     ref = oracle.reference_spectrum(ref_frames, spec.bins)
@@ -271,7 +276,7 @@ def precision_forms(args, torch, cg, dev):
         errs, sps = form_errors(spec, pool_np[0], ref_np, sample_mags, 4096)
         fft_t = lines[0]["tooth_transform_ms"]
         for line in lines:
-            line["cpu_baseline"] = {"value": sps * n * 2 / 1e9, "unit": "GB/s", "cores": None,
+            line["cpu_baseline"] = {"value": sps * n * 2 / 1e9, "unit": "GB/s", "cores": blas_threads(),
                                     "kind": "oracle",
                                     "sample": "FP64 DFT amplitudes of the first 4096 frames"}
             line["amplitude_error_vs_oracle"] = errs[line["config"]["form"]]
@@ -375,7 +380,7 @@ def warm_forms(args, torch, cg, dev):
                                         "within_1e-3_fwhm": float(np.mean(eo[oc] <= 1e-3)),
                                         "median_fwhm": float(np.median(eo[oc]))}
             line["cpu_baseline"] = {"value": orc["n"] * n * 2 / orc["dt"] / 1e9, "unit": "GB/s",
-                                    "cores": None, "kind": "oracle",
+                                    "cores": blas_threads(), "kind": "oracle",
                                     "sample": f"cold-start FP64 oracle on the first {orc['n']} "
                                               f"frames of batch 0, {orc['dt']:.1f} s"}
         print(json.dumps(line), flush=True)
@@ -515,7 +520,7 @@ def fano_workload(args, torch, cg, dev):
         conv = ora["status"][:m] == 0
         err = np.abs(params0[:m, 0] - ora["params"][:m, 0]) / FANO_W
         line["cpu_baseline"] = {"value": ns_cpu * n * sbytes / dt / 1e9, "unit": "GB/s",
-                                "spectra_per_s": ns_cpu / dt, "cores": None, "kind": "oracle",
+                                "spectra_per_s": ns_cpu / dt, "cores": blas_threads(), "kind": "oracle",
                                 "sample": f"first {ns_cpu} frames of batch 0 (FP64 oracle's "
                                           f"whole Fano path), {dt:.1f} s",
                                 "host": host_info(),
@@ -685,17 +690,12 @@ def psd_workload(args, torch, cg, dev):
     n_max = int(fs * windows[-1])
     _log(f"generating {n_max} displacement samples ...")
     t0 = time.perf_counter()
-    xs = torch.empty(n_max, dtype=torch.float32, device=dev)
-    chunk = 1 << 24
-    pos = 0
-    host_first = None
-    for c in range(0, n_max, chunk):
-        part = synth.make_displacement(min(chunk, n_max - c), fs, f0, q, drive=1e-3, floor=1e-2,
-                                       drift=1e-6, seed=1000 + c // chunk)
-        if host_first is None:
-            host_first = part[:int(fs)].copy()
-        xs[pos:pos + part.shape[0]] = torch.from_numpy(part).to(dev)
-        pos += part.shape[0]
+    # one continuous series (the generator integrates it in chunks itself)
+    host = synth.make_displacement(n_max, fs, f0, q, drive=1e-3, floor=1e-2, drift=1e-6,
+                                   seed=1000)
+    host_first = host[:int(fs)].copy()
+    xs = torch.from_numpy(host).to(dev)
+    del host
     _log(f"  {time.perf_counter() - t0:.1f} s")
     rows = []
     for w in windows:
@@ -738,7 +738,7 @@ def psd_workload(args, torch, cg, dev):
         dt = time.perf_counter() - t0
         g1 = cg.psd_welch(xs[:int(fs)], fs, seg, k_lo, nb).cpu().numpy()
         line["cpu_baseline"] = {"value": int(fs) * 4 / dt / 1e9, "unit": "GB/s",
-                                "cores": None, "kind": "oracle",
+                                "cores": blas_threads(), "kind": "oracle",
                                 "sample": f"the 1 s window: FP64 Welch at the band bins and the "
                                           f"fit, {dt:.1f} s", "host": host_info()}
         line["parity_1s"] = {"psd_max_rel_err": float(np.max(np.abs(g1 - o_psd) / o_psd)),

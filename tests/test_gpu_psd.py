@@ -27,6 +27,7 @@ import paper_2307_12988_amd as cg  # noqa: E402
 
 DEV = torch.device("cuda:0")
 FS, F0, Q = 1.0e6, 23.7e3, 115.0
+PSD_RTOL = 1e-5
 
 
 def _say(m):
@@ -44,7 +45,10 @@ def test_psd_matches_oracle(seg, n):
     want = opsd.welch_band(x.astype(np.float64), FS, seg, k_lo, nb)
     rel = np.abs(got - want) / want
     _say(f"seg={seg} n={n}: {nb} bins, max rel {rel.max():.2e}, median {np.median(rel):.2e}")
-    assert rel.max() <= 1e-3
+    # FP32 FFT of 2^13..2^16 complex points: about eps * sqrt(passes) of the
+    # segment's RMS bin per bin; the band's bins sit within a few decades of
+    # that RMS, and the FP64 sums over segments add nothing (measured <= 9e-7)
+    assert rel.max() <= PSD_RTOL
 
 
 def test_psd_band_edges_and_errors():
@@ -54,7 +58,9 @@ def test_psd_band_edges_and_errors():
     for k_lo, nb in ((0, 5), (8192 - 4, 5)):
         got = cg.psd_welch(xt, FS, 16384, k_lo, nb).cpu().numpy()
         want = opsd.welch_band(x.astype(np.float64), FS, 16384, k_lo, nb)
-        assert np.max(np.abs(got - want) / want) <= 1e-3
+        rel = np.max(np.abs(got - want) / want)
+        _say(f"bins {k_lo}..{k_lo + nb - 1}: max rel {rel:.2e}")
+        assert rel <= PSD_RTOL
     with pytest.raises(cg.CombGpuError):
         cg.psd_welch(xt[:1000].contiguous(), FS, 16384, 10, 10)       # shorter than a segment
     with pytest.raises(cg.CombGpuError):
