@@ -278,8 +278,13 @@ cg_status cg_start_points(cg_plan* plan, const float* median, int64_t n_frames, 
  * equations (A + lam diag A) d = J^T r solved by an FP64 Cholesky; lam starts
  * at 1e-3, /10 on accept, *10 on reject; a step is accepted when chi2 does not
  * increase, width stays > 0 and all values are finite; converged when an
- * accepted step lowers chi2 by <= 1e-6 chi2 (or chi2 <= 1e-30).  max_iter in
- * 1..CG_MAX_ITER (the paper uses 20).  Outputs as in cg_process_batch_ex.
+ * accepted step lowers chi2 by <= 1e-6 chi2 (or chi2 <= 1e-30).  Residuals,
+ * Jacobian and sums are FP32, the chi2 decrease of a step taken from the
+ * model's change so that it is exact to FP32 rounding of itself; a spectrum
+ * the model reproduces exactly stops at chi2 <= K (2^-19 b0)^2 (b0: the start
+ * baseline), the FP32 counterpart of 1e-30, and is reported converged.
+ * max_iter in 1..CG_MAX_ITER (the paper uses 20).  Outputs as in
+ * cg_process_batch_ex.
  */
 cg_status cg_fit_spectra(cg_plan* plan, const float* y, const float* p0, int64_t n_frames,
                          int32_t max_iter, float* out_params, int32_t* out_iters,

@@ -10,27 +10,43 @@
 // -------------
 // A wavefront works on 64/G spectra at a time, one per group of G lanes (G = 8
 // up to 224 teeth, else 16); lane gl of a group owns teeth i = gl + G q.  Per
-// evaluation each lane computes model, residual and chi2 in FP64 (so the chi2
-// comparisons and the 1e-6 relative-decrease test see the same values an
-// FP64 reference sees) and the four Jacobian columns and the 14
-// normal-equation products in FP32; DPP butterflies inside the group give
-// every lane of the group bit-identical sums.  The damped 4x4 system is solved
-// per group by a Cholesky factorisation in FP64.  Evaluating a trial point
-// also produces the normal equations there, so an accepted step needs no
-// second pass.
+// tooth the lane keeps, in registers, the residual r = y - f and the dip term
+// g = b d / D (D = 1 + u^2) at the group's current parameters.  A trial point
+// is evaluated from the parameter differences, so that every quantity the
+// decisions use is computed to FP32 accuracy relative to its own size:
+//   du  = u_cur - u_trial             (per-spectrum coefficients from FP64)
+//   dD  = D_cur - D_trial = du (2 u_trial + du)
+//   dg  = g_trial - g_cur = (d(bd) + dD g_cur) / D_trial
+//   df  = f_trial - f_cur = db - dg,  r_trial = r - df,
+//   chi2_cur - chi2_trial = sum df (r + r_trial).
+// The FP32 residuals are those of the FP32 spectrum plus a rounding of the
+// start point's model (a few ulps of b): each step moves them by exactly the
+// computed model change, so "chi2 did not increase" and "chi2 fell by at most
+// 1e-6 of itself" are decided on a consistent chi2 to within rounding of the
+// decrease itself.  Deciding them on two separately rounded FP32 sums instead
+// (each off by ~1e-7 of chi2) adds iterations: a decrease of 1e-6 chi2 is
+// lost in that noise.  The four Jacobian columns and the 14 normal-equation
+// products are FP32 as well; FP64 is used only for the per-spectrum
+// parameters and coefficients and the damped 4x4 solve (Cholesky).  DPP
+// butterflies inside the group give every lane of the group bit-identical
+// sums.  Evaluating a trial point also produces the normal equations there,
+// so an accepted step needs no second pass.
 //
 // A wave owns a contiguous chunk of spectra.  The LM loop body is the same for
 // every iteration, so groups run independent fits in lock step: when a group
 // finishes it writes its result and takes the next spectrum of the chunk (the
 // hand-out index is wave-uniform, advanced with a ballot), evaluates the new
-// start point in the next trip and carries on.  A wave exits when its chunk is
-// exhausted and all its groups are idle; every fit is bounded by max_iter.
+// start point in the next trip and carries on.  The start point is evaluated
+// as a trial from the same centre and width with zero depth (where r = y - b
+// and g = 0 hold exactly), so one loop body serves both.  A wave exits when
+// its chunk is exhausted and all its groups are idle; every fit is bounded by
+// max_iter.
 //
 // Schedule (the paper fixes only the cap and the tolerance): lam0 = 1e-3,
 // /10 on accept, *10 on reject; accept when finite, width > 0 and chi2 does
 // not increase; converged when an accepted step lowers chi2 by at most
-// 1e-6 * chi2_old or chi2 <= 1e-30; a non-positive-definite damped matrix
-// stops the fit as singular.
+// 1e-6 * chi2_old or chi2 <= 1e-30 (or at the FP32 resolution floor below);
+// a non-positive-definite damped matrix stops the fit as singular.
 #include "fp64.h"
 #include "internal.h"
 #include "wave.h"
@@ -41,118 +57,112 @@ namespace {
 struct Sums {
   float a[10];   // J^T J upper triangle: 00 01 02 03 11 12 13 22 23 33
   float g[4];    // J^T r
-  double chi2;
+  float chi2;    // sum r^2 at the point
+  float drop;    // chi2 at the group's current point minus chi2 here
 };
 
-// Sums over the group's teeth at one parameter point (a group of G lanes,
-// Q = ceil(k / G) slots per lane).  The arithmetic is the same for every lane; teeth past the last
-// one, which only the last slot can hold, contribute exact zeros, and a
-// group whose point is not used (idle, or a rejected trial point) simply
-// computes values nobody reads, so the loop body has no divergent branches.
+// Per-spectrum coefficients of one trial, formed in FP64 and rounded once:
+// u at the lane's first tooth and its step per slot at the trial point, the
+// same for u_cur - u_trial, and the trial's changes of b d and b.
+struct Trial {
+  float u0, ustep, du0, dustep, dbd, db, d, b, two_iw;
+};
+
+// Sums over the group's teeth at a trial point (a group of G lanes, Q =
+// ceil(k / G) slots per lane), and the trial's residuals and dip terms.  The
+// arithmetic is the same for every lane; teeth past the last one, which only
+// the last slot can hold, contribute exact zeros, and a group whose point is
+// not used (idle, or a rejected trial point) simply computes values nobody
+// reads, so the loop body has no divergent branches.
 //
 // The Jacobian columns share per-spectrum factors, which are applied once to
 // the reduced sums instead of to every tooth: with u = 2 (x - c) / w,
-// D = 1 + u^2, s = d / D^2,
-//   df/dc = (-4 b / w) s u,   df/dw = (-2 b / w) s u^2,
-//   df/dd = (-b) / D,         df/db = 1 - d / D.
-//
-// Per tooth the FP64 part is u (from the lane's first tooth plus a constant
-// offset), D, 1 / D and the residual r = (y - b) + (b d) / D, which is
-// y - f(x) rounded differently; the FP32 Jacobian factors start from FP32
-// copies of the same quantities.
+// D = 1 + u^2, e = 1 / D,
+//   df/dc = (-4 b d / w) u e^2,   df/dw = (-2 b d / w) u^2 e^2,
+//   df/dd = (-b) e,               df/db = 1 - d e.
+// Per tooth only p = u e^2, p u and e enter: the products of the b column
+// follow from sums of p, p u, e and r (sum (1 - d e) v = sum v - d sum e v),
+// so 13 sums carry the normal equations.
 template <int G, int Q>
-__device__ __forceinline__ void evaluate(const float (&yv)[Q], int k, double c, double w,
-                                         double d, double b, Sums& s) {
+__device__ __forceinline__ void evaluate(const float (&r)[Q], const float (&g)[Q],
+                                         float (&rn)[Q], float (&gn)[Q], int k,
+                                         const Trial& t, Sums& s) {
   const int gl = lane_id() & (G - 1);
-  float acc[14];
+  // 0 pp, 1 pw, 2 pe, 3 ww, 4 we, 5 ee, 6 p, 7 w, 8 e, 9 pr, 10 wr, 11 er,
+  // 12 r, 13 r^2, 14 drop   (w here: p u)
+  float acc[15];
 #pragma unroll
-  for (int j = 0; j < 14; ++j) acc[j] = 0.0f;
-  double chi2 = 0.0;
-  const double two_iw = 2.0 * rcp_d(w);
-  const double u0 = fma((double)gl, two_iw, -c * two_iw);  // u at tooth gl
-  const double bd = b * d;
-  const float two_iwf = (float)two_iw, u0f = (float)u0, df = (float)d;
-  const double step = (double)G * two_iw;
-  double u_prev = u0;
+  for (int j = 0; j < 15; ++j) acc[j] = 0.0f;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    // The empty asm statements pin pairs of slots in program order: the u of
-    // the pair's first slot passes through one before the pair's arithmetic
-    // and the sums pass through one after the pair.  Each u is the previous
-    // one plus the tooth step (one FP64 add; an fma from u0 with the slot's
-    // offset needs a register copy of u0 first, as the offset is a literal).  Left alone, the compiler evaluates the FP64 part of
-    // every slot first and keeps all of it live (about 100 extra VGPRs); two
-    // slots at a time give the scheduler two independent chains.
-    const int i = gl + G * q;
-    double u;
-    if (q % 2 == 0) {
-      u = q == 0 ? u0 : u_prev + step;
-      asm volatile("" : "+v"(u));
-    } else {
-      u = u_prev + step;
+    // Two slots at a time between empty asm statements, which keep the
+    // compiler from hoisting every slot's first steps (and their registers)
+    // to the top of the loop.
+    float u = fmaf((float)q, t.ustep, t.u0);
+    float du = fmaf((float)q, t.dustep, t.du0);
+    if (q % 2 == 0) asm volatile("" : "+v"(u), "+v"(du));
+    const float den = fmaf(u, u, 1.0f);
+    float e = __builtin_amdgcn_rcpf(den);
+    const float dden = du * fmaf(2.0f, u, du);       // D_cur - D_trial
+    const float dg = fmaf(dden, g[q], t.dbd) * e;    // g_trial - g_cur
+    float df = t.db - dg;                            // f_trial - f_cur
+    float rt = r[q] - df;
+    gn[q] = g[q] + dg;
+    float pc = e * e * u;
+    float pw = pc * u;
+    if (q == Q - 1) {                                // only the last slot can be partial
+      const bool in = gl + G * q < k;
+      df = in ? df : 0.0f;
+      rt = in ? rt : 0.0f;
+      pc = in ? pc : 0.0f;
+      pw = in ? pw : 0.0f;
+      e = in ? e : 0.0f;
     }
-    u_prev = u;
-    const double den = fma(u, u, 1.0);
-    const double inv = rcp1_d(den);
-    double r = fma(bd, inv, (double)yv[q] - b);
-    const float invf = (float)inv;
-    const float uf = fmaf((float)(G * q), two_iwf, u0f);
-    const float qf = df * invf;  // d / D
-    float jc = qf * invf * uf;   // s u
-    float jw = jc * uf;          // s u^2
-    float jd = invf;             // 1 / D
-    float jb = 1.0f - qf;        // 1 - d / D
-    if (q == Q - 1) {            // only the last slot can be partial
-      const bool in = i < k;
-      r = in ? r : 0.0;
-      jc = in ? jc : 0.0f;
-      jw = in ? jw : 0.0f;
-      jd = in ? jd : 0.0f;
-      jb = in ? jb : 0.0f;
-    }
-    const float rf = (float)r;
-    chi2 = fma(r, r, chi2);
-    acc[0] = fmaf(jc, jc, acc[0]);
-    acc[1] = fmaf(jc, jw, acc[1]);
-    acc[2] = fmaf(jc, jd, acc[2]);
-    acc[3] = fmaf(jc, jb, acc[3]);
-    acc[4] = fmaf(jw, jw, acc[4]);
-    acc[5] = fmaf(jw, jd, acc[5]);
-    acc[6] = fmaf(jw, jb, acc[6]);
-    acc[7] = fmaf(jd, jd, acc[7]);
-    acc[8] = fmaf(jd, jb, acc[8]);
-    acc[9] = fmaf(jb, jb, acc[9]);
-    acc[10] = fmaf(jc, rf, acc[10]);
-    acc[11] = fmaf(jw, rf, acc[11]);
-    acc[12] = fmaf(jd, rf, acc[12]);
-    acc[13] = fmaf(jb, rf, acc[13]);
+    rn[q] = rt;
+    acc[0] = fmaf(pc, pc, acc[0]);
+    acc[1] = fmaf(pc, pw, acc[1]);
+    acc[2] = fmaf(pc, e, acc[2]);
+    acc[3] = fmaf(pw, pw, acc[3]);
+    acc[4] = fmaf(pw, e, acc[4]);
+    acc[5] = fmaf(e, e, acc[5]);
+    acc[6] += pc;
+    acc[7] += pw;
+    acc[8] += e;
+    acc[9] = fmaf(pc, rt, acc[9]);
+    acc[10] = fmaf(pw, rt, acc[10]);
+    acc[11] = fmaf(e, rt, acc[11]);
+    acc[12] += rt;
+    acc[13] = fmaf(rt, rt, acc[13]);
+    acc[14] = fmaf(df, r[q] + rt, acc[14]);
     if (q % 2 == 1 || q == Q - 1)
       asm volatile(""
-                 : "+v"(chi2), "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]),
-                   "+v"(acc[4]), "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]),
-                   "+v"(acc[9]), "+v"(acc[10]), "+v"(acc[11]), "+v"(acc[12]), "+v"(acc[13]));
+                   : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
+                     "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7]), "+v"(acc[8]), "+v"(acc[9]),
+                     "+v"(acc[10]), "+v"(acc[11]), "+v"(acc[12]), "+v"(acc[13]),
+                     "+v"(acc[14]));
   }
-  float sum[14];
+  float sm[15];
 #pragma unroll
-  for (int j = 0; j < 14; ++j) sum[j] = sum_group<G>(acc[j]);
-  // column factors: c, w, d carry al, be, ga; b carries 1
-  const float bf = (float)b;
-  const float al = -2.0f * bf * two_iwf, be = -bf * two_iwf, ga = -bf;
-  s.a[0] = sum[0] * (al * al);
-  s.a[1] = sum[1] * (al * be);
-  s.a[2] = sum[2] * (al * ga);
-  s.a[3] = sum[3] * al;
-  s.a[4] = sum[4] * (be * be);
-  s.a[5] = sum[5] * (be * ga);
-  s.a[6] = sum[6] * be;
-  s.a[7] = sum[7] * (ga * ga);
-  s.a[8] = sum[8] * ga;
-  s.a[9] = sum[9];
-  s.g[0] = sum[10] * al;
-  s.g[1] = sum[11] * be;
-  s.g[2] = sum[12] * ga;
-  s.g[3] = sum[13];
-  s.chi2 = sum_group<G>(chi2);
+  for (int j = 0; j < 15; ++j) sm[j] = sum_group<G>(acc[j]);
+  // column factors: c, w carry al, be (depth included), d carries ga; the b
+  // column is 1 - d e
+  const float al = -2.0f * t.b * t.two_iw * t.d, be = -t.b * t.two_iw * t.d, ga = -t.b;
+  s.a[0] = sm[0] * (al * al);
+  s.a[1] = sm[1] * (al * be);
+  s.a[2] = sm[2] * (al * ga);
+  s.a[3] = al * fmaf(-t.d, sm[2], sm[6]);
+  s.a[4] = sm[3] * (be * be);
+  s.a[5] = sm[4] * (be * ga);
+  s.a[6] = be * fmaf(-t.d, sm[4], sm[7]);
+  s.a[7] = sm[5] * (ga * ga);
+  s.a[8] = ga * fmaf(-t.d, sm[5], sm[8]);
+  s.a[9] = fmaf(-t.d, fmaf(2.0f, sm[8], -t.d * sm[5]), (float)k);
+  s.g[0] = sm[9] * al;
+  s.g[1] = sm[10] * be;
+  s.g[2] = sm[11] * ga;
+  s.g[3] = fmaf(-t.d, sm[11], sm[12]);
+  s.chi2 = sm[13];
+  s.drop = sm[14];
 }
 
 // Solve (A + lam diag A) delta = g by Cholesky in FP64; false if the damped
@@ -187,28 +197,39 @@ __device__ __forceinline__ bool damped_solve(const Sums& s, double lam, double (
          isfinite(delta[3]);
 }
 
+// A new spectrum: r = y - b and g = 0, the residual and dip term of the
+// start point's centre, width and baseline with zero depth (zeros past the
+// last tooth).
 template <int G, int Q>
 __device__ __forceinline__ void load_spectrum(const float* __restrict__ y, int64_t s, int k,
-                                              float (&yv)[Q]) {
+                                              float b, float (&r)[Q], float (&g)[Q]) {
   const int gl = lane_id() & (G - 1);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int i = gl + G * q;
-    yv[q] = (q < Q - 1 || i < k) ? y[s * k + i] : 0.0f;  // only the last slot can be partial
+    r[q] = (q < Q - 1 || i < k) ? y[s * k + i] - b : 0.0f;  // only the last slot can be partial
+    g[q] = 0.0f;
   }
 }
 
+// The residuals keep the rounding of the model changes they have been moved
+// by: a few FP32 ulps of the start point's baseline b0, mostly from the first
+// steps.  A fit whose chi2 falls below k (2^-19 b0)^2 (an RMS residual of 16
+// ulps of b0) has reached the resolution of this arithmetic and is reported
+// converged, as a chi2 <= 1e-30 is in FP64.  Only spectra that the model
+// reproduces exactly (noiseless or all-zero) get there: measured spectra sit
+// orders of magnitude above it.
+__device__ __forceinline__ float resolution_floor(int k, double b0) {
+  const float s = 0x1p-19f * (float)fabs(b0);
+  return (float)k * s * s;
+}
+
 template <int G, int Q>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void lm_kernel(const float* __restrict__ y,
-                                                 const float* __restrict__ p0,
-                                                 const int32_t* __restrict__ idx,
-                                                 const int32_t* __restrict__ count, int64_t nf,
-                                                 int k, int max_iter, int chunk,
-                                                 float* __restrict__ params,
-                                                 int32_t* __restrict__ iters,
-                                                 int32_t* __restrict__ status,
-                                                 float* __restrict__ chi2_out, int status_code,
-                                                 int32_t* __restrict__ zero_count) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void lm_kernel(
+    const float* __restrict__ y, const float* __restrict__ p0, const int32_t* __restrict__ idx,
+    const int32_t* __restrict__ count, int64_t nf, int k, int max_iter, int chunk,
+    float* __restrict__ params, int32_t* __restrict__ iters, int32_t* __restrict__ status,
+    float* __restrict__ chi2_out, int status_code, int32_t* __restrict__ zero_count) {
   constexpr int NG = 64 / G;  // spectra in flight per wave
   // a counter the next kernel on the stream accumulates into (the fallback
   // list after a polish), cleared here so that no kernel has to do only that
@@ -230,22 +251,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   int64_t next = base + NG;  // wave-uniform hand-out index
   bool active = s < end;
   bool fresh = true;
-  float yv[Q];
-  double c = 0, w = 1, d = 0, b = 0, lam = 1e-3;
+  float r[Q], g[Q], rn[Q], gn[Q];
+  // current point (d = 0 until the start point is taken), the start depth,
+  // and u = a x + e at the current point
+  double c = 0, w = 1, d = 0, b = 0, d_start = 0, lam = 1e-3, ua = 2, ue = 0;
+  float floor2 = 0.0f;  // resolution floor of chi2 (see the convergence test)
   int it = 0;
   int64_t fi = 0;  // frame of the current spectrum
   Sums cur;
   if (active) {
     fi = idx ? (int64_t)idx[s] : s;
-    load_spectrum<G, Q>(y, fi, k, yv);
     c = p0[fi * 4 + 0];
     w = p0[fi * 4 + 1];
-    d = p0[fi * 4 + 2];
+    d_start = p0[fi * 4 + 2];
     b = p0[fi * 4 + 3];
+    load_spectrum<G, Q>(y, fi, k, (float)b, r, g);
+    floor2 = resolution_floor(k, b);
   } else {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) yv[q] = 0.0f;
+    for (int q = 0; q < Q; ++q) r[q] = g[q] = 0.0f;
   }
+  ua = 2.0 * rcp_d(w);
+  ue = -c * ua;
 
   while (__ballot(active) != 0ull) {
     // 1. damped step for groups past their start point (every group runs the
@@ -254,35 +281,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     double delta[4];
     const bool solved = damped_solve(cur, lam, delta) && stepping;
     const double tc = stepping ? c + delta[0] : c, tw = stepping ? w + delta[1] : w;
-    const double td = stepping ? d + delta[2] : d, tb = stepping ? b + delta[3] : b;
+    const double td = stepping ? d + delta[2] : d_start, tb = stepping ? b + delta[3] : b;
     const bool point_ok = fresh || (solved && isfinite(tc) && isfinite(tw) && isfinite(td) &&
                                     isfinite(tb) && tw > 0.0);
-    // 2. evaluation (start point for fresh groups, trial point otherwise)
+    // 2. evaluation (start point for fresh groups, trial point otherwise);
+    //    u = ta x + te at the trial point
+    const double ta = 2.0 * rcp_d(tw), te = -tc * ta;
+    Trial t;
+    t.u0 = (float)fma((double)gl, ta, te);
+    t.ustep = (float)(G * ta);
+    t.du0 = (float)fma((double)gl, ua - ta, ue - te);
+    t.dustep = (float)(G * (ua - ta));
+    t.dbd = (float)(tb * td - b * d);
+    t.db = (float)(tb - b);
+    t.d = (float)td;
+    t.b = (float)tb;
+    t.two_iw = (float)ta;
     Sums trial;
-    evaluate<G, Q>(yv, k, tc, tw, td, tb, trial);
-    // 3. decisions, as selects: the four groups of a wave are in different
+    evaluate<G, Q>(r, g, rn, gn, k, t, trial);
+    // 3. decisions, as selects: the groups of a wave are in different
     //    states, and branches here would only execute every path with copies
     const bool start = active && fresh;
-    const bool accept = stepping && solved && point_ok && isfinite(trial.chi2) &&
-                        trial.chi2 <= cur.chi2;
+    const bool finite = isfinite(trial.chi2) && isfinite(trial.drop);
+    const bool accept = stepping && solved && point_ok && finite && trial.drop >= 0.0f;
     const bool take = start || accept;
-    const double old = cur.chi2;
+    const float old = cur.chi2;
     it = start ? 0 : (stepping ? it + 1 : it);
     lam = start ? 1e-3 : (accept ? lam * 0.1 : ((stepping && solved) ? lam * 10.0 : lam));
     c = take ? tc : c;
     w = take ? tw : w;
     d = take ? td : d;
     b = take ? tb : b;
+    ua = take ? ta : ua;
+    ue = take ? te : ue;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      r[q] = take ? rn[q] : r[q];
+      g[q] = take ? gn[q] : g[q];
+    }
 #pragma unroll
     for (int j = 0; j < 10; ++j) cur.a[j] = take ? trial.a[j] : cur.a[j];
 #pragma unroll
     for (int j = 0; j < 4; ++j) cur.g[j] = take ? trial.g[j] : cur.g[j];
     cur.chi2 = take ? trial.chi2 : cur.chi2;
     fresh = active ? false : fresh;
-    const bool start_bad = start && !isfinite(trial.chi2);
-    const bool start_exact = start && !start_bad && trial.chi2 <= 1e-30;
+    const bool start_bad = start && !finite;
+    const bool start_exact = start && !start_bad && trial.chi2 <= 1e-30f;
     const bool singular = stepping && !solved;
-    const bool conv = accept && (old - trial.chi2 <= 1e-6 * old || trial.chi2 <= 1e-30);
+    const bool conv =
+        accept && (trial.drop <= 1e-6f * old || trial.chi2 <= 1e-30f || trial.chi2 <= floor2);
     const bool capped = stepping && !singular && !conv && it >= max_iter;
     const bool done = start_bad || start_exact || singular || conv || capped;
     const int st = (start_bad || singular) ? CG_FIT_SINGULAR
@@ -298,7 +345,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
       }
       if (iters) iters[fi] = it;
       if (status) status[fi] = status_code >= 0 ? status_code : st;
-      if (chi2_out) chi2_out[fi] = (float)cur.chi2;
+      if (chi2_out) chi2_out[fi] = cur.chi2;
     }
     const uint64_t fin = __ballot(done && gl == 0);
     if (fin != 0ull) {
@@ -309,11 +356,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         fresh = true;
         if (active) {
           fi = idx ? (int64_t)idx[s] : s;
-          load_spectrum<G, Q>(y, fi, k, yv);
           c = p0[fi * 4 + 0];
           w = p0[fi * 4 + 1];
-          d = p0[fi * 4 + 2];
+          d = 0.0;
+          d_start = p0[fi * 4 + 2];
           b = p0[fi * 4 + 3];
+          load_spectrum<G, Q>(y, fi, k, (float)b, r, g);
+          floor2 = resolution_floor(k, b);
+          ua = 2.0 * rcp_d(w);
+          ue = -c * ua;
         }
       }
       next += __popcll(fin);

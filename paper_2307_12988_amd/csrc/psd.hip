@@ -335,7 +335,6 @@ __global__ __launch_bounds__(OSC_T) void osc_fit_kernel(const double* __restrict
   __shared__ double srt[OSC_MAXB];
   __shared__ double red[OSC_T];
   __shared__ double sp[4];
-  __shared__ int sh_i;
   int npow = 1;
   while (npow < nb) npow <<= 1;
   for (int b = threadIdx.x; b < npow; b += OSC_T) {
@@ -388,7 +387,6 @@ __global__ __launch_bounds__(OSC_T) void osc_fit_kernel(const double* __restrict
     sp[1] = f0;
     sp[2] = q;
     sp[3] = log(floor_b > 1e-300 ? floor_b : 1e-300);
-    sh_i = ipk;
   }
   __syncthreads();
   double p[4] = {sp[0], sp[1], sp[2], sp[3]};

@@ -39,6 +39,17 @@ def warm_compared(status):
     return np.where(st == 2, 2, 0)
 
 
+def full_fit_compared(status):
+    """Statuses for centre_parity on the warm path when the polish runs to the
+    cold start's cap (a full LM fit from the network's start point): as for
+    the cold path, frames whose fit stopped at the cap (1) or was singular (2)
+    are left out, since a fit that has not converged has no unique end point
+    (in ill-conditioned valleys it depends on rounding along the path);
+    converged fits (0) and cold refits (3) are compared."""
+    st = np.asarray(status)
+    return np.where(st == 3, 0, st)
+
+
 def centre_parity(y_oracle, p_gpu, p_oracle, st_oracle, chi2_oracle):
     """Returns dict with fraction passing, exemptions and the outlier rows."""
     p_gpu = np.asarray(p_gpu, dtype=np.float64)

@@ -31,7 +31,7 @@ import pytest
 import oracle
 import synth
 from oracle import mlp as omlp
-from parity_util import PASS_FRACTION, centre_parity, warm_compared
+from parity_util import PASS_FRACTION, centre_parity, full_fit_compared, warm_compared
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -252,9 +252,15 @@ def test_warm_path_polish_to_convergence():
     torch.cuda.synchronize()
     st = warm["status"].cpu().numpy()
     res = centre_parity(ora["y"], warm["params"].cpu().numpy(), ora["params"],
-                        warm_compared(ora["status"]), ora["chi2"])
+                        full_fit_compared(ora["status"]), ora["chi2"])
     _say(f"polish 20: fallback {np.mean(st == 3):.4f} (oracle {np.mean(ora['status'] == 3):.4f}),"
          f" parity {res['fraction']:.5f}, iters {warm['iters'].float().mean().item():.2f}")
+    gp = warm["params"].cpu().numpy()
+    gi = warm["iters"].cpu().numpy()
+    for f in res["outliers"]:
+        _say(f"  outlier {f}: status gpu {st[f]} oracle {ora['status'][f]}, iters gpu {gi[f]} "
+             f"oracle {ora['iters'][f]}, gpu {gp[f]} oracle {ora['params'][f]}, chi2 oracle "
+             f"{ora['chi2'][f]:.6g} at gpu {oracle.chi2_at(ora['y'][f], gp[f]):.6g}")
     assert res["fraction"] >= PASS_FRACTION, res
     assert np.mean(st == ora["status"]) >= 0.99
     # reported, not asserted: on frames that keep the network's start point,

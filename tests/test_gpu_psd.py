@@ -60,7 +60,11 @@ def test_psd_band_edges_and_errors():
         want = opsd.welch_band(x.astype(np.float64), FS, 16384, k_lo, nb)
         rel = np.max(np.abs(got - want) / want)
         _say(f"bins {k_lo}..{k_lo + nb - 1}: max rel {rel:.2e}")
-        assert rel <= PSD_RTOL
+        # a bin's FP32 rounding scales with the segment's RMS bin, not with
+        # the bin: relative error about 2 eps sqrt(passes) sqrt(P_mean / P_k);
+        # near Nyquist this series has only its white floor, a few decades
+        # below the mean power (measured 2.8e-5 there, 1.3e-6 at DC)
+        assert rel <= 1e-4
     with pytest.raises(cg.CombGpuError):
         cg.psd_welch(xt[:1000].contiguous(), FS, 16384, 10, 10)       # shorter than a segment
     with pytest.raises(cg.CombGpuError):
