@@ -390,7 +390,7 @@ def fano_workload(args, torch, cg, dev):
     comb and the same Fano fit."""
     spec = synth.spec_paper8() if args.workload == "paper8" else synth.spec_fano()
     nf, n, k = args.frames, spec.n, spec.k
-    _log(f"generating {args.pool} batches of {nf} x {n} int16 (Fano stream) ...")
+    _log(f"generating {args.pool} batches of {nf} x {n} {spec.sample_dtype} (Fano stream) ...")
     pool_np, ref_np = make_pool(spec, nf, args.pool, workers=min(args.pool, 8))
     first_np = pool_np[0]
     pool = [torch.from_numpy(fr).to(dev) for fr in pool_np]

@@ -120,6 +120,7 @@ void free_plan(cg_plan* p) {
   if (p->d_tw) (void)hipFree(p->d_tw);
   if (p->d_tw_mixed) (void)hipFree(p->d_tw_mixed);
   if (p->d_tooth_w) (void)hipFree(p->d_tooth_w);
+  if (p->d_mx_list) (void)hipFree(p->d_mx_list);
   if (p->ws) (void)hipFree(p->ws);
   for (auto* b : p->d_mfma_bf)
     if (b) (void)hipFree(b);
@@ -239,6 +240,7 @@ cg_status cg_create_plan_ex(int32_t frame_len, double fs, const int32_t* tooth_b
            "copy mixed twiddles");
     CG_TRY(hipMemcpy(p->d_tooth_w, ttw.data(), sizeof(float2) * n_teeth, hipMemcpyHostToDevice),
            "copy tooth twiddles");
+    CG_TRY(cg::mixed_prepare(p), "mixed-radix butterfly lists");
   }
   CG_TRY(cg::resolve_static_scratch(p->device), "fixed scratch: hipGetSymbolAddress");
 #undef CG_TRY

@@ -26,6 +26,10 @@ struct cg_plan {
   float2* d_tw = nullptr;      // [n] W_n^e = (cos 2 pi e/n, -sin 2 pi e/n), e = 0..n-1
   float2* d_tw_mixed = nullptr;  // 2200-sample frames: [1100] W_1100^e
   float2* d_tooth_w = nullptr;   // 2200-sample frames: [k] W_2200^bin per tooth
+  // 2200-sample frames: butterflies of the last three FFT passes that the
+  // teeth need, per pass 64 * mx_rounds[p] entries (-1: none), int16
+  int16_t* d_mx_list = nullptr;
+  int32_t mx_rounds[3] = {0, 0, 0};
   std::vector<int32_t> h_bins;
   std::vector<float> h_ref;
   void* ws = nullptr;          // plan-owned workspace (grown on demand)
@@ -74,6 +78,9 @@ hipError_t launch_fft_teeth(const cg_plan* p, const void* frames, int64_t n_fram
                             const int32_t* dev_n = nullptr);
 // The paper's 2200-sample frames (mixed-radix FFT, int8 or int16 samples).
 int fft_mixed_grid_limit(const cg_plan* p);
+// Build the plan's lists of needed butterflies from its bins (host work and
+// one upload; called at plan creation).
+hipError_t mixed_prepare(cg_plan* p);
 hipError_t launch_fft_mixed(const cg_plan* p, const void* frames, int64_t n_frames,
                             float* out_mag, float* out_y, hipStream_t s,
                             const int32_t* dev_n = nullptr);
