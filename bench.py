@@ -50,11 +50,11 @@ SEED = 1
 # for the kernel sources they were taken on:
 # kernel -> (sources, sha256 prefix of their concatenation, read B, write B)
 TRAFFIC = {
-    "fft_teeth": (("fft_teeth.hip",), "c8c18ee7d4f30561", 131306.6 * 2 * 1024, 56323.6 * 1024),
+    "fft_teeth": (("fft_teeth.hip",), "2f0f3ebdc945fa9a", 131307.4 * 2 * 1024, 56323.4 * 1024),
     "median_start": (("median.hip", "wave.h"), "1ac469519e98187a", 39067.4 * 2 * 1024,
                      1024.0 * 1024),
-    "lm_fit": (("lm.hip", "wave.h", "fp64.h"), "920363e16bdc8fa4", 28744.6 * 2 * 1024,
-               1550.7 * 1024),
+    "lm_fit": (("lm.hip", "wave.h", "fp64.h"), "9a4cb94731e7d12f", 28754.1 * 2 * 1024,
+               1551.4 * 1024),
 }
 
 
@@ -190,6 +190,43 @@ def form_errors(spec, frames, ref_frames, mags_by_form, n_sample):
     return out, n_sample / dt
 
 
+def precision_crossover(torch, cg, dev, frames, fs):
+    """Tooth-transform time of the FFT and the matrix-core forms against the
+    tooth count on the same frames (131072 x 4096 int16): the FFT's cost is
+    nearly independent of K, the matrix products' grows with it, so below
+    some K a matrix-core form is faster.  Timing only (the frames' own comb
+    has 220 teeth; the other tooth sets are the interleaved layouts)."""
+    nf, n = frames.shape
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    for k in (16, 32, 48, 64, 96, 128, 160, 220, 320, 440):
+        bins = synth.tooth_bins_interleaved(n, k)
+        plan = cg.Plan(n, fs, bins, np.ones(k, dtype=np.float32))
+        mag = torch.empty((nf, k), dtype=torch.float32, device=dev)
+        row = {"teeth": k}
+        for name, flag in (("fft_fp32", cg.DFT_FFT), ("mfma_bf16x3", cg.DFT_MFMA_BF16X3),
+                           ("mfma_fp16x2", cg.DFT_MFMA_FP16X2), ("mfma_fp16", cg.DFT_MFMA_FP16)):
+            plan.teeth(frames, flags=flag, want_mag=True, want_y=False, out_mag=mag)  # warm-up
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(stream)
+            for _ in range(3):
+                plan.teeth(frames, flags=flag, want_mag=True, want_y=False, out_mag=mag)
+            ev[1].record(stream)
+            torch.cuda.synchronize(dev)
+            row[name + "_ms"] = ev[0].elapsed_time(ev[1]) / 3
+        rows.append(row)
+        _log(f"  K={k}: " + ", ".join(f"{a} {b:.3f}" for a, b in row.items() if a != "teeth"))
+        plan.close()
+    cross = {}
+    for name in ("mfma_bf16x3", "mfma_fp16x2", "mfma_fp16"):
+        faster = [r["teeth"] for r in rows if r[name + "_ms"] < r["fft_fp32_ms"]]
+        cross[name] = max(faster) if faster else None
+    return {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1,
+            "config": {"workload": f"tooth-transform time vs tooth count: {nf} frames x {n} int16",
+                       "form": "crossover"},
+            "rows": rows, "largest_K_where_faster_than_fft": cross}
+
+
 def precision_forms(args, torch, cg, dev):
     spec = synth.spec_precision()
     nf = 131072 if args.frames == 65536 else args.frames
@@ -265,6 +302,8 @@ def precision_forms(args, torch, cg, dev):
     for line in lines:
         print(json.dumps(line), flush=True)
     plan.close()
+    if args.crossover:
+        print(json.dumps(precision_crossover(torch, cg, dev, pool[0], spec.fs)), flush=True)
 
 
 def warm_forms(args, torch, cg, dev):
@@ -882,6 +921,8 @@ def multistream(args, torch, cg, dev):
     due = [t0 + float(rng.random()) * 1e-3 for _ in range(ns)]
     nxt = [burst(i) for i in range(ns)]
     dropped = 0
+    late = []          # how late each burst was handed over (the producer's own lag)
+    late_drop = []     # the same for the dropped ones
     last_log = t0
     while True:
         now = time.perf_counter()
@@ -891,11 +932,15 @@ def multistream(args, torch, cg, dev):
         if due[i] > now:
             continue
         b = nxt[i]
+        lag = now - due[i]
         try:
             pipe.put(i, b, seq[i])
             seq[i] += 1
+            if len(late) < 1_000_000:
+                late.append(lag)
         except cg.RingFull:
             dropped += 1
+            late_drop.append(lag)
         due[i] += b.shape[0] * specs[i].n / specs[i].fs
         nxt[i] = burst(i)
         if now - last_log > 30:
@@ -925,7 +970,13 @@ def multistream(args, torch, cg, dev):
                          "dev_lat_p99_ms": s2["dev_lat_p99_ms"],
                          "dev_lat_max_ms": s2["dev_lat_max_ms"],
                          "dev_span_p50_ms": s2["dev_span_p50_ms"],
-                         "bursts": s2["bursts"]},
+                         "bursts": s2["bursts"],
+                         "dispatcher_launch_max_ms": s2["launch_max_ms"],
+                         "dispatcher_pass_max_ms": s2["dispatch_pass_max_ms"],
+                         "producer_lag_p99_ms": 1e3 * float(np.percentile(late, 99)) if late else None,
+                         "producer_lag_max_ms": 1e3 * float(np.max(late)) if late else None,
+                         "dropped_lag_median_ms": 1e3 * float(np.median(late_drop))
+                         if late_drop else None},
         "autotune": tune,
         "stream_classes": classes,
     }
@@ -958,6 +1009,8 @@ def main():
                          "multistream: 16 interleaved streams through the ring pipeline")
     ap.add_argument("--seconds", type=float, default=20.0,
                     help="multistream: length of the paced phase (600 for the 10-minute run)")
+    ap.add_argument("--crossover", action="store_true",
+                    help="precision: also time the tooth transforms against the tooth count")
     ap.add_argument("--phase1", type=float, default=5.0,
                     help="multistream: length of the maximum-rate phase")
     ap.add_argument("--slots", type=int, default=8, help="multistream: ring slots per stream")

@@ -495,8 +495,13 @@ cg_status cg_pipeline_drain(cg_pipeline* pipe, int32_t timeout_ms);
  * latency publish -> results p50, p99, max (ms), GPU-clock span graph start
  * -> results p50 (ms), bursts that completed ahead of an earlier burst of
  * their stream (re-sorted on read).  In dry-run mode the GPU-clock figures
- * are the host clock's. */
+ * are the host clock's.  Percentiles come from a uniform sample of at most
+ * 2^20 bursts of the whole run, maxima from every burst.  With n_out >=
+ * CG_PIPE_NSTATS_EX two more: the longest single burst launch on the
+ * dispatcher thread (ms) and its longest pass over launches and completion
+ * polling (ms). */
 #define CG_PIPE_NSTATS 15
+#define CG_PIPE_NSTATS_EX 17
 cg_status cg_pipeline_stats(cg_pipeline* pipe, double* out, int32_t n_out);
 
 /*

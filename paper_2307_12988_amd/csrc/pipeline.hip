@@ -78,6 +78,7 @@ enum SlotState : int { FREE = 0, WRITING = 1, QUEUED = 2, RUNNING = 3, DONE = 4 
 
 struct Burst {
   int stream, slot;
+  int lane = 0;  // compute lane the dispatcher launched it on
 };
 
 struct PipeSlot {
@@ -134,6 +135,28 @@ struct PipeStream {
 
 }  // namespace
 
+// At most `cap` values kept as a uniform random sample of all values seen
+// (reservoir sampling, fixed seed), plus the exact maximum.
+struct LatSample {
+  std::vector<float> v;
+  uint64_t seen = 0, rng = 0x9e3779b97f4a7c15ull;
+  double max = 0.0;
+  void add(double x, size_t cap) {
+    const double xf = (double)(float)x;  // as kept in the sample
+    max = seen == 0 ? xf : std::max(max, xf);
+    ++seen;
+    if (v.size() < cap) {
+      v.push_back((float)x);
+      return;
+    }
+    rng ^= rng << 13;
+    rng ^= rng >> 7;
+    rng ^= rng << 17;
+    const uint64_t j = rng % seen;
+    if (j < cap) v[(size_t)j] = (float)x;
+  }
+};
+
 struct cg_pipeline {
   bool dry = false;
   bool keep = false;
@@ -154,9 +177,13 @@ struct cg_pipeline {
   int64_t out_of_order = 0;  // bursts completed ahead of an earlier one of their stream
   double bytes = 0.0;
   double t_first = -1.0, t_last = 0.0;
-  std::vector<float> lat_ms;      // host clock: publish -> completion seen
-  std::vector<float> dev_lat_ms;  // GPU clock: publish (mapped) -> results written
-  std::vector<float> dev_span_ms; // GPU clock: graph start -> results written
+  // latency samples: a uniform sample (reservoir) of every completed burst
+  // and the exact maxima
+  LatSample lat_ms;      // host clock: publish -> completion seen
+  LatSample dev_lat_ms;  // GPU clock: publish (mapped) -> results written
+  LatSample dev_span_ms; // GPU clock: graph start -> results written
+  double launch_max_ms = 0.0;  // longest single burst launch on the dispatcher
+  double loop_gap_max_ms = 0.0;  // longest dispatcher pass (launches + polling)
   double clk_hz = 1e8;            // GPU wall-clock rate
   // host time = GPU clock / clk_hz - offset; offset estimated by the
   // smallest launch-to-start gap over the current and the previous 0.1 s
@@ -168,6 +195,7 @@ namespace cg {
 namespace {
 
 constexpr size_t kLatKeep = 1 << 20;
+constexpr size_t kLaunchPerPass = 32;
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -319,9 +347,10 @@ hipError_t alloc_slot(const PipeStream& ps, PipeSlot& sl, int cap, bool host_rin
 // launch one burst (dispatcher thread, no lock held): the copy, then the
 // slot's graph and its completion event on the next compute lane of the
 // stream.  No other thread enqueues on the stream's HIP streams.
-hipError_t launch_burst(cg_pipeline* P, const Burst& q) {
+hipError_t launch_burst(cg_pipeline* P, Burst& q) {
   PipeStream& ps = P->st[q.stream];
   PipeSlot& sl = ps.slots[q.slot];
+  q.lane = ps.next_lane;
   hipStream_t lane = ps.lanes[ps.next_lane];
   ps.next_lane = (ps.next_lane + 1) % (int)ps.lanes.size();
   hipError_t e = hipSuccess;
@@ -347,10 +376,7 @@ hipError_t launch_burst(cg_pipeline* P, const Burst& q) {
   return e;
 }
 
-template <typename T>
-void keep_sample(std::vector<T>& v, double x) {
-  if (v.size() < kLatKeep) v.push_back((T)x);
-}
+void keep_sample(LatSample& v, double x) { v.add(x, kLatKeep); }
 
 // bookkeeping of a completed burst (lock held)
 void complete(cg_pipeline* P, const Burst& q, double t) {
@@ -398,6 +424,8 @@ void dispatcher(cg_pipeline* P) {
   if (!P->dry) (void)hipSetDevice(P->device);
   std::vector<Burst> todo, inflight, finished, still;
   std::vector<hipError_t> errs;
+  std::vector<char> blocked;
+  double launch_ms = 0.0, gap_ms = 0.0;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(P->mu);
@@ -407,18 +435,25 @@ void dispatcher(cg_pipeline* P) {
                        [&] { return P->stop || !P->queue.empty(); });
         if (P->stop && P->queue.empty() && inflight.empty()) return;
       }
-      todo.assign(P->queue.begin(), P->queue.end());
-      P->queue.clear();
+      // at most kLaunchPerPass bursts per pass, so that completions (which
+      // free slots) are polled between launches when many bursts arrive at
+      // once
+      const size_t take = std::min(P->queue.size(), kLaunchPerPass);
+      todo.assign(P->queue.begin(), P->queue.begin() + (std::ptrdiff_t)take);
+      P->queue.erase(P->queue.begin(), P->queue.begin() + (std::ptrdiff_t)take);
       P->in_flight += (int64_t)todo.size();
       for (auto& q : todo) P->st[q.stream].slots[q.slot].state = RUNNING;
     }
+    const double pass_start = now_s();
     // launches, in publish order (slot contents are only read here and by
     // the dispatcher's completion step while the slot is RUNNING)
     for (auto& q : todo) {
       if (P->dry) {
         P->st[q.stream].slots[q.slot].t_launch = now_s();
       } else {
+        const double t0 = now_s();
         const hipError_t e = launch_burst(P, q);
+        launch_ms = std::max(launch_ms, (now_s() - t0) * 1e3);
         if (e != hipSuccess) {
           std::lock_guard<std::mutex> lk(P->mu);
           P->failed = true;
@@ -428,26 +463,37 @@ void dispatcher(cg_pipeline* P) {
       inflight.push_back(q);
     }
     todo.clear();
-    // completions: events polled without the lock
+    // completions: events polled without the lock.  Bursts on one compute
+    // lane (one HIP stream) complete in launch order, so once a lane's oldest
+    // running burst is not done its later ones are not queried.
     const double t = now_s();
     finished.clear();
     still.clear();
     errs.clear();
+    blocked.assign(P->st.size() * (size_t)CG_PIPE_MAX_LANES, 0);
     for (auto& q : inflight) {
       PipeSlot& sl = P->st[q.stream].slots[q.slot];
+      char& lane_blocked = blocked[(size_t)q.stream * CG_PIPE_MAX_LANES + q.lane];
       bool done;
       if (P->dry) {
         done = t >= sl.t_pub + 1e-6 * P->dry_us * sl.n;
+      } else if (lane_blocked) {
+        done = false;
       } else {
         const hipError_t qe = hipEventQuery(sl.done);
         done = qe != hipErrorNotReady;
         if (done && qe != hipSuccess) errs.push_back(qe);
+        lane_blocked = !done;
       }
       (done ? finished : still).push_back(q);
     }
     inflight.swap(still);
-    if (!finished.empty() || !errs.empty()) {
+    gap_ms = std::max(gap_ms, (now_s() - pass_start) * 1e3);
+    if (!finished.empty() || !errs.empty() || launch_ms > P->launch_max_ms ||
+        gap_ms > P->loop_gap_max_ms) {
       std::lock_guard<std::mutex> lk(P->mu);
+      P->launch_max_ms = std::max(P->launch_max_ms, launch_ms);
+      P->loop_gap_max_ms = std::max(P->loop_gap_max_ms, gap_ms);
       if (!errs.empty()) {
         P->failed = true;
         P->fail_detail = std::string("pipeline burst: ") + hipGetErrorString(errs.front());
@@ -699,12 +745,14 @@ cg_status cg_pipeline_stats(cg_pipeline* P, double* out, int32_t n_out) {
   if (!P || !out) return CG_ERR_NULL;
   if (n_out < CG_PIPE_NSTATS) return CG_ERR_INVALID_ARG;
   std::vector<float> lat, dlat, dspan;
-  double span;
+  double span, lat_max, dlat_max;
   {
     std::lock_guard<std::mutex> lk(P->mu);
-    lat = P->lat_ms;
-    dlat = P->dev_lat_ms;
-    dspan = P->dev_span_ms;
+    lat = P->lat_ms.v;
+    dlat = P->dev_lat_ms.v;
+    dspan = P->dev_span_ms.v;
+    lat_max = P->lat_ms.max;
+    dlat_max = P->dev_lat_ms.max;
     span = P->t_first >= 0 ? P->t_last - P->t_first : 0.0;
     out[0] = (double)P->bursts;
     out[1] = (double)P->frames;
@@ -717,22 +765,23 @@ cg_status cg_pipeline_stats(cg_pipeline* P, double* out, int32_t n_out) {
     std::nth_element(v.begin(), v.begin() + i, v.end());
     return v[i];
   };
-  auto vmax = [](const std::vector<float>& v) -> double {
-    return v.empty() ? 0.0 : (double)*std::max_element(v.begin(), v.end());
-  };
   out[4] = span;
   out[5] = pct(lat, 0.5);
   out[6] = pct(lat, 0.99);
-  out[7] = vmax(lat);
+  out[7] = lat_max;
   out[8] = span > 0 ? out[2] / span : 0.0;
   out[9] = span > 0 ? out[1] / span : 0.0;
   out[10] = pct(dlat, 0.5);
   out[11] = pct(dlat, 0.99);
-  out[12] = vmax(dlat);
+  out[12] = dlat_max;
   out[13] = pct(dspan, 0.5);
   {
     std::lock_guard<std::mutex> lk(P->mu);
     out[14] = (double)P->out_of_order;
+    if (n_out >= CG_PIPE_NSTATS_EX) {
+      out[15] = P->launch_max_ms;
+      out[16] = P->loop_gap_max_ms;
+    }
   }
   return CG_OK;
 }

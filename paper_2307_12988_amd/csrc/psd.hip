@@ -16,9 +16,11 @@
 // and 2 X[k] = (Z[k] + conj Z[M-k]) - i W_L^k (Z[k] - conj Z[M-k]) at the
 // band bins; a block of psd_rows takes the row pair (r, 128 - r), which
 // holds both Z[k] and Z[M - k] of its bins.  The column and row FFTs are
-// Stockham radix-4 (and one radix-2) passes in LDS.  Segments run in chunks;
-// each chunk's per-segment powers are added into FP64 sums in segment order
-// (deterministic), and the last step scales them into the density.
+// Stockham radix-4 (and one radix-2) passes in LDS.  Segment means come from
+// FP64 sums of half-segments (each sample read once).  Segments run in
+// chunks; each chunk's per-segment powers are added into FP64 sums in a fixed
+// order (groups of 64 consecutive segments, then the groups), and the last
+// step scales them into the density.
 //
 // Resonance fit: one block, FP64 throughout: S(f) = A / ((f0^2 - f^2)^2 +
 // (f0 f / Q)^2) + B fitted on ln S over the band by Levenberg-Marquardt
@@ -111,26 +113,29 @@ __global__ void psd_tables_kernel(int L, int k_lo, int n_bins, float* __restrict
   }
 }
 
-// Segment means (FP64 sums), one block per segment.
-__global__ __launch_bounds__(256) void psd_means_kernel(const float* __restrict__ x, int L,
-                                                        int64_t seg0, float* __restrict__ mean) {
-  __shared__ double part[256];
-  const int64_t start = (seg0 + blockIdx.x) * (int64_t)(L / 2);
+// FP64 sums of the half-segments (hop = L / 2 samples) h = h0 .. h0 + nh - 1,
+// one block each; segment s covers half-segments s and s + 1, so its mean is
+// (hsum[s] + hsum[s + 1]) / L and every sample is read once.
+__global__ __launch_bounds__(256) void psd_halfsum_kernel(const float* __restrict__ x, int hop,
+                                                          int64_t h0, double* __restrict__ hsum) {
+  __shared__ double part[4];
+  const float2* src = reinterpret_cast<const float2*>(x + (h0 + blockIdx.x) * (int64_t)hop);
   double acc = 0.0;
-  for (int t = threadIdx.x; t < L; t += 256) acc += (double)x[start + t];
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-    __syncthreads();
+  for (int t = threadIdx.x; t < hop / 2; t += 256) {
+    const float2 v = src[t];
+    acc += (double)v.x + (double)v.y;
   }
-  if (threadIdx.x == 0) mean[blockIdx.x] = (float)(part[0] / (double)L);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) hsum[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
 // Column step: block (segment s of the chunk, columns c0 .. c0 + 15).
 template <int N1>
 __global__ __launch_bounds__(256) void psd_cols_kernel(const float* __restrict__ x, int64_t seg0,
-                                                       const float* __restrict__ mean,
+                                                       const double* __restrict__ hsum,
                                                        const float* __restrict__ win,
                                                        const cxf* __restrict__ wm,
                                                        cxf* __restrict__ yg) {
@@ -141,7 +146,7 @@ __global__ __launch_bounds__(256) void psd_cols_kernel(const float* __restrict__
   const int s = blockIdx.y;
   const int c0 = blockIdx.x * PSD_COLS;
   const int64_t start = (seg0 + s) * (int64_t)(L / 2);
-  const float m = mean[s];
+  const float m = (float)((hsum[s] + hsum[s + 1]) / (double)L);
   for (int e = threadIdx.x; e < PSD_N2; e += 256) tw[e] = wm[e * N1];  // W_128^e = W_M^(e N1)
   for (int p = threadIdx.x; p < PSD_COLS * PSD_N2; p += 256) {
     const int cl = p % PSD_COLS, n2 = p / PSD_COLS;
@@ -203,13 +208,27 @@ __global__ __launch_bounds__(128) void psd_rows_kernel(const cxf* __restrict__ y
   }
 }
 
-// Adds the chunk's per-segment powers into the FP64 sums, in segment order.
-__global__ void psd_accumulate_kernel(const float* __restrict__ pseg, int n_seg, int n_bins,
+// The chunk's per-segment powers into the FP64 sums in a fixed order: groups
+// of PSD_GROUP consecutive segments summed in segment order (psd_part), then
+// the groups in order (psd_accumulate).
+constexpr int PSD_GROUP = 64;
+__global__ void psd_part_kernel(const float* __restrict__ pseg, int n_seg, int n_bins,
+                                double* __restrict__ part) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bins) return;
+  const int s0 = blockIdx.y * PSD_GROUP;
+  const int s1 = s0 + PSD_GROUP < n_seg ? s0 + PSD_GROUP : n_seg;
+  double a = 0.0;
+  for (int s = s0; s < s1; ++s) a += (double)pseg[(int64_t)s * n_bins + b];
+  part[(int64_t)blockIdx.y * n_bins + b] = a;
+}
+
+__global__ void psd_accumulate_kernel(const double* __restrict__ part, int n_groups, int n_bins,
                                       double* __restrict__ acc) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_bins) return;
   double a = acc[b];
-  for (int s = 0; s < n_seg; ++s) a += (double)pseg[(int64_t)s * n_bins + b];
+  for (int g = 0; g < n_groups; ++g) a += part[(int64_t)g * n_bins + b];
   acc[b] = a;
 }
 
@@ -235,25 +254,35 @@ __global__ void psd_scale_kernel(const double* __restrict__ acc, int n_bins, int
 constexpr int OSC_T = 256;
 constexpr int OSC_MAXB = 2048;
 
-__device__ double block_sum(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int h = OSC_T / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
+// Sums over the block of NV values per thread: butterflies inside each
+// wavefront, then the four wavefronts' partial sums through LDS (two
+// barriers per call whatever NV is).  Every thread gets every sum.
+template <int NV>
+__device__ void block_sums(double (&v)[NV], double* red) {
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[u] += __shfl_xor(v[u], o);
   }
-  const double r = red[0];
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) red[wv * NV + u] = v[u];
+  }
   __syncthreads();
-  return r;
+#pragma unroll
+  for (int u = 0; u < NV; ++u)
+    v[u] = red[u] + red[NV + u] + red[2 * NV + u] + red[3 * NV + u];
+  __syncthreads();
 }
 
-// ln S and its gradient with respect to (ln A, f0, Q, ln B) at frequency f.
-__device__ __forceinline__ void osc_eval(double f, const double (&p)[4], double& lns,
-                                         double (&g)[4]) {
+// ln S and its gradient with respect to (ln A, f0, Q, ln B) at frequency f
+// (ea = A, eb = B).
+__device__ __forceinline__ void osc_eval(double f, const double (&p)[4], double ea, double eb,
+                                         double& lns, double (&g)[4]) {
   const double f0 = p[1], q = p[2];
   const double dd = f0 * f0 - f * f;
   const double den = dd * dd + (f0 * f / q) * (f0 * f / q);
-  const double ea = exp(p[0]), eb = exp(p[3]);
   const double res = ea / den;
   const double s = res + eb;
   lns = log(s);
@@ -266,24 +295,30 @@ __device__ __forceinline__ void osc_eval(double f, const double (&p)[4], double&
 }
 
 // Sums of J^T J (10), J^T r (4) and chi2 over the band at p.
-__device__ void osc_sums(const double* __restrict__ lny, const double* __restrict__ fr, int nb,
+__device__ void osc_sums(const double* __restrict__ lny, double f_first, double df, int nb,
                          const double (&p)[4], double* red, double (&a)[10], double (&g)[4],
                          double& chi2) {
-  double la[10] = {0}, lg[4] = {0}, lc = 0.0;
+  double v[15] = {0};  // 0..9 J^T J, 10..13 J^T r, 14 chi2
+  const double ea = exp(p[0]), eb = exp(p[3]);
   for (int b = threadIdx.x; b < nb; b += OSC_T) {
     double lns, j[4];
-    osc_eval(fr[b], p, lns, j);
+    osc_eval(f_first + df * (double)b, p, ea, eb, lns, j);
     const double r = lny[b] - lns;
-    lc += r * r;
+    v[14] += r * r;
     int o = 0;
+#pragma unroll
     for (int u = 0; u < 4; ++u) {
-      lg[u] += j[u] * r;
-      for (int v = u; v < 4; ++v) la[o++] += j[u] * j[v];
+      v[10 + u] += j[u] * r;
+#pragma unroll
+      for (int w = u; w < 4; ++w) v[o++] += j[u] * j[w];
     }
   }
-  for (int o = 0; o < 10; ++o) a[o] = block_sum(la[o], red);
-  for (int u = 0; u < 4; ++u) g[u] = block_sum(lg[u], red);
-  chi2 = block_sum(lc, red);
+  block_sums<15>(v, red);
+#pragma unroll
+  for (int o = 0; o < 10; ++o) a[o] = v[o];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) g[u] = v[10 + u];
+  chi2 = v[14];
 }
 
 __device__ bool chol4_solve(const double (&a)[10], double lam, const double (&g)[4],
@@ -331,17 +366,19 @@ __global__ __launch_bounds__(OSC_T) void osc_fit_kernel(const double* __restrict
                                                         double f_first, double df, int max_iter,
                                                         double tol, double* __restrict__ out) {
   __shared__ double lny[OSC_MAXB];
-  __shared__ double fr[OSC_MAXB];
   __shared__ double srt[OSC_MAXB];
-  __shared__ double red[OSC_T];
+  __shared__ double val[OSC_MAXB];
+  __shared__ double red[4 * 15];
   __shared__ double sp[4];
+  __shared__ int pk[4];
   int npow = 1;
   while (npow < nb) npow <<= 1;
   for (int b = threadIdx.x; b < npow; b += OSC_T) {
     if (b < nb) {
-      lny[b] = log(psd[b]);
-      fr[b] = f_first + df * (double)b;
-      srt[b] = psd[b];
+      const double v = psd[b];
+      lny[b] = log(v);
+      srt[b] = v;
+      val[b] = v;
     } else {
       srt[b] = INFINITY;
     }
@@ -364,23 +401,36 @@ __global__ __launch_bounds__(OSC_T) void osc_fit_kernel(const double* __restrict
       __syncthreads();
     }
   }
+  // the peak: the first bin holding the band's largest value
+  {
+    int ib = threadIdx.x < nb ? (int)threadIdx.x : 0;
+    for (int b = threadIdx.x + OSC_T; b < nb; b += OSC_T)
+      if (val[b] > val[ib]) ib = b;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int oth = __shfl_xor(ib, o);
+      if (val[oth] > val[ib] || (val[oth] == val[ib] && oth < ib)) ib = oth;
+    }
+    if ((threadIdx.x & 63) == 0) pk[threadIdx.x >> 6] = ib;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     // start point: peak, floor, half-width
-    int ipk = 0;
-    for (int b = 1; b < nb; ++b)
-      if (psd[b] > psd[ipk]) ipk = b;
+    int ipk = pk[0];
+    for (int w = 1; w < 4; ++w)
+      if (val[pk[w]] > val[ipk] || (val[pk[w]] == val[ipk] && pk[w] < ipk)) ipk = pk[w];
     const int qn = nb / 4 > 1 ? nb / 4 : 1;
     const double floor_b = (qn % 2 == 1) ? srt[qn / 2] : 0.5 * (srt[qn / 2 - 1] + srt[qn / 2]);
-    const double half = floor_b + 0.5 * (psd[ipk] - floor_b);
+    const double half = floor_b + 0.5 * (val[ipk] - floor_b);
     int lo = ipk, hi = ipk;
-    while (lo > 0 && psd[lo] > half) --lo;
-    while (hi < nb - 1 && psd[hi] > half) ++hi;
-    const double f0 = fr[ipk];
-    double width = fr[hi] - fr[lo];
+    while (lo > 0 && val[lo] > half) --lo;
+    while (hi < nb - 1 && val[hi] > half) ++hi;
+    const double f0 = f_first + df * (double)ipk;
+    double width = df * (double)(hi - lo);
     width = width > df ? width : df;
     double q = f0 / width;
     q = q > 1.0 ? q : 1.0;
-    double ex = psd[ipk] - floor_b;
+    double ex = val[ipk] - floor_b;
     ex = ex > 1e-300 ? ex : 1e-300;
     const double a = ex * f0 * f0 * f0 * f0 / (q * q);
     sp[0] = log(a);
@@ -391,7 +441,7 @@ __global__ __launch_bounds__(OSC_T) void osc_fit_kernel(const double* __restrict
   __syncthreads();
   double p[4] = {sp[0], sp[1], sp[2], sp[3]};
   double a[10], g[4], chi2;
-  osc_sums(lny, fr, nb, p, red, a, g, chi2);
+  osc_sums(lny, f_first, df, nb, p, red, a, g, chi2);
   double lam = 1e-3;
   int it = 0, status = CG_FIT_MAX_ITER;
   while (it < max_iter) {
@@ -406,7 +456,7 @@ __global__ __launch_bounds__(OSC_T) void osc_fit_kernel(const double* __restrict
     const bool ok_pt = isfinite(t[0]) && isfinite(t[1]) && isfinite(t[2]) && isfinite(t[3]) &&
                        t[1] > 0.0 && t[2] > 0.0;
     double at[10], gt[4], ct = INFINITY;
-    if (ok_pt) osc_sums(lny, fr, nb, t, red, at, gt, ct);
+    if (ok_pt) osc_sums(lny, f_first, df, nb, t, red, at, gt, ct);
     if (!(ok_pt && isfinite(ct) && ct <= chi2)) {
       lam *= 10.0;
       continue;
@@ -437,16 +487,19 @@ __global__ __launch_bounds__(OSC_T) void osc_fit_kernel(const double* __restrict
 
 template <int N1>
 hipError_t run_chunk(const float* x, int64_t seg0, int nseg, int k_lo, int n_bins,
-                     const float* win, const cxf* wm, const cxf* wband, float* mean, cxf* yg,
-                     float* pseg, double* acc, hipStream_t s) {
+                     const float* win, const cxf* wm, const cxf* wband, double* hsum, cxf* yg,
+                     float* pseg, double* part, double* acc, hipStream_t s) {
   constexpr int L = 2 * N1 * PSD_N2;
-  hipLaunchKernelGGL(psd_means_kernel, dim3(nseg), dim3(256), 0, s, x, L, seg0, mean);
+  const int groups = (nseg + PSD_GROUP - 1) / PSD_GROUP;
+  hipLaunchKernelGGL(psd_halfsum_kernel, dim3(nseg + 1), dim3(256), 0, s, x, L / 2, seg0, hsum);
   hipLaunchKernelGGL((psd_cols_kernel<N1>), dim3(N1 / PSD_COLS, nseg), dim3(256), 0, s, x, seg0,
-                     mean, win, wm, yg);
+                     hsum, win, wm, yg);
   hipLaunchKernelGGL((psd_rows_kernel<N1>), dim3(PSD_N2 / 2 + 1, nseg), dim3(128), 0, s, yg, wm,
                      wband, k_lo, n_bins, pseg);
-  hipLaunchKernelGGL(psd_accumulate_kernel, dim3((n_bins + 255) / 256), dim3(256), 0, s, pseg,
-                     nseg, n_bins, acc);
+  hipLaunchKernelGGL(psd_part_kernel, dim3((n_bins + 255) / 256, groups), dim3(256), 0, s, pseg,
+                     nseg, n_bins, part);
+  hipLaunchKernelGGL(psd_accumulate_kernel, dim3((n_bins + 255) / 256), dim3(256), 0, s, part,
+                     groups, n_bins, acc);
   return hipGetLastError();
 }
 
@@ -456,11 +509,13 @@ size_t a256p(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t psd_workspace_bytes(int64_t chunk_segments, int seg_len, int n_bins) {
   const size_t M = (size_t)seg_len / 2;
+  const size_t groups = ((size_t)chunk_segments + PSD_GROUP - 1) / PSD_GROUP;
   return a256p(sizeof(float) * (size_t)seg_len) + a256p(sizeof(cxf) * M) +
          a256p(sizeof(cxf) * (size_t)n_bins) + a256p(sizeof(double) * (size_t)n_bins) +
-         a256p(sizeof(float) * (size_t)chunk_segments) +
+         a256p(sizeof(double) * ((size_t)chunk_segments + 1)) +
          a256p(sizeof(cxf) * M * (size_t)chunk_segments) +
-         a256p(sizeof(float) * (size_t)n_bins * (size_t)chunk_segments);
+         a256p(sizeof(float) * (size_t)n_bins * (size_t)chunk_segments) +
+         a256p(sizeof(double) * (size_t)n_bins * groups);
 }
 
 hipError_t launch_psd(const float* x, int64_t n, double fs, int seg_len, int k_lo, int n_bins,
@@ -477,11 +532,13 @@ hipError_t launch_psd(const float* x, int64_t n, double fs, int seg_len, int k_l
   c += a256p(sizeof(cxf) * (size_t)n_bins);
   double* acc = reinterpret_cast<double*>(c);
   c += a256p(sizeof(double) * (size_t)n_bins);
-  float* mean = reinterpret_cast<float*>(c);
-  c += a256p(sizeof(float) * (size_t)chunk_segments);
+  double* hsum = reinterpret_cast<double*>(c);
+  c += a256p(sizeof(double) * ((size_t)chunk_segments + 1));
   cxf* yg = reinterpret_cast<cxf*>(c);
   c += a256p(sizeof(cxf) * (size_t)M * (size_t)chunk_segments);
   float* pseg = reinterpret_cast<float*>(c);
+  c += a256p(sizeof(float) * (size_t)n_bins * (size_t)chunk_segments);
+  double* part = reinterpret_cast<double*>(c);
   hipLaunchKernelGGL(psd_tables_kernel, dim3((seg_len + 255) / 256), dim3(256), 0, s, seg_len,
                      k_lo, n_bins, win, wm, wband);
   hipLaunchKernelGGL(psd_zero_kernel, dim3((n_bins + 255) / 256), dim3(256), 0, s, acc, n_bins);
@@ -490,16 +547,16 @@ hipError_t launch_psd(const float* x, int64_t n, double fs, int seg_len, int k_l
     const int nseg = (int)(n_seg - seg0 < chunk_segments ? n_seg - seg0 : chunk_segments);
     switch (seg_len) {
       case 16384:
-        e = run_chunk<64>(x, seg0, nseg, k_lo, n_bins, win, wm, wband, mean, yg, pseg, acc, s);
+        e = run_chunk<64>(x, seg0, nseg, k_lo, n_bins, win, wm, wband, hsum, yg, pseg, part, acc, s);
         break;
       case 32768:
-        e = run_chunk<128>(x, seg0, nseg, k_lo, n_bins, win, wm, wband, mean, yg, pseg, acc, s);
+        e = run_chunk<128>(x, seg0, nseg, k_lo, n_bins, win, wm, wband, hsum, yg, pseg, part, acc, s);
         break;
       case 65536:
-        e = run_chunk<256>(x, seg0, nseg, k_lo, n_bins, win, wm, wband, mean, yg, pseg, acc, s);
+        e = run_chunk<256>(x, seg0, nseg, k_lo, n_bins, win, wm, wband, hsum, yg, pseg, part, acc, s);
         break;
       case 131072:
-        e = run_chunk<512>(x, seg0, nseg, k_lo, n_bins, win, wm, wband, mean, yg, pseg, acc, s);
+        e = run_chunk<512>(x, seg0, nseg, k_lo, n_bins, win, wm, wband, hsum, yg, pseg, part, acc, s);
         break;
       default:
         e = hipErrorInvalidValue;

@@ -438,7 +438,8 @@ PIPE_DRY_RUN = 0x2
 PIPE_HOST_RING = 0x4
 STATS_FIELDS = ("bursts", "frames", "bytes", "overflows", "seconds", "lat_p50_ms", "lat_p99_ms",
                 "lat_max_ms", "bytes_per_s", "frames_per_s", "dev_lat_p50_ms", "dev_lat_p99_ms",
-                "dev_lat_max_ms", "dev_span_p50_ms", "out_of_order")
+                "dev_lat_max_ms", "dev_span_p50_ms", "out_of_order", "launch_max_ms",
+                "dispatch_pass_max_ms")
 
 
 class RingFull(_lib.CombGpuError):
