@@ -568,7 +568,7 @@ def host_ingest(args, torch, cg, dev):
     n, k = spec.n, spec.k
     burst = 32768
     n_pool = 8
-    slots, lanes = args.slots if args.slots != 8 else 6, 2
+    slots, lanes = args.slots if args.slots is not None else 6, 2
     _log(f"generating {n_pool} host bursts of {burst} x {n} int16 ...")
     pool_np, ref_np = make_pool(spec, burst, n_pool, workers=min(n_pool, 8))
     plan = cg.Plan(n, spec.fs, spec.bins, np.ones(k, dtype=np.float32))
@@ -891,7 +891,7 @@ def multistream(args, torch, cg, dev):
     parity = None
     if not args.no_cpu_baseline:
         parity = multistream_parity(args, torch, cg, dev, specs, plans, pools, gen, w, tune)
-    pipe = cg.Pipeline(plans, fl, slots_per_stream=args.slots, max_burst_frames=4096)
+    pipe = cg.Pipeline(plans, fl, slots_per_stream=args.slots or 64, max_burst_frames=4096)
     rng = np.random.default_rng(7)
 
     def burst(i):
@@ -916,7 +916,7 @@ def multistream(args, torch, cg, dev):
     s1 = pipe.stats()
     pipe.close()
     # phase 2: paced at the digitiser rate of every stream
-    pipe = cg.Pipeline(plans, fl, slots_per_stream=args.slots, max_burst_frames=4096)
+    pipe = cg.Pipeline(plans, fl, slots_per_stream=args.slots or 64, max_burst_frames=4096)
     t0 = time.perf_counter()
     due = [t0 + float(rng.random()) * 1e-3 for _ in range(ns)]
     nxt = [burst(i) for i in range(ns)]
@@ -958,7 +958,7 @@ def multistream(args, torch, cg, dev):
         "data": "synthetic",
         "config": {"workload": f"{ns} interleaved streams, frame lengths 512-8192, 64-440 teeth, "
                                f"bursts of 256-4096 frames, learned warm start, ring pipeline",
-                   "streams": ns, "slots_per_stream": args.slots,
+                   "streams": ns, "slots_per_stream": args.slots or 64,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "spectra_per_s": s1["frames_per_s"],
         "phase1_max_rate": {k: s1[k] for k in s1}, "phase1_ring_full_events": full,
@@ -1013,7 +1013,8 @@ def main():
                     help="precision: also time the tooth transforms against the tooth count")
     ap.add_argument("--phase1", type=float, default=5.0,
                     help="multistream: length of the maximum-rate phase")
-    ap.add_argument("--slots", type=int, default=8, help="multistream: ring slots per stream")
+    ap.add_argument("--slots", type=int, default=None,
+                    help="ring slots per stream (multistream: 64, host_ingest: 6)")
     ap.add_argument("--hw-queues", type=int, default=0,
                     help="hardware queues per process (GPU_MAX_HW_QUEUES, 1..32; 0 = leave "
                          "the environment as it is)")
