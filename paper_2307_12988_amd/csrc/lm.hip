@@ -32,15 +32,18 @@
 // sums.  Evaluating a trial point also produces the normal equations there,
 // so an accepted step needs no second pass.
 //
-// A wave owns a contiguous chunk of spectra.  The LM loop body is the same for
-// every iteration, so groups run independent fits in lock step: when a group
-// finishes it writes its result and takes the next spectrum of the chunk (the
-// hand-out index is wave-uniform, advanced with a ballot), evaluates the new
-// start point in the next trip and carries on.  The start point is evaluated
+// A block of eight wavefronts owns a contiguous range of spectra (eight
+// chunks).  The LM loop body is the same for every iteration, so groups run
+// independent fits in lock step: when a group finishes it writes its result
+// and takes the next spectrum of the block's range (a wavefront reserves as
+// many as it has finished groups with one LDS atomic add), evaluates the new
+// start point in the next trip and carries on.  Sharing the range across the
+// block's wavefronts evens out their work: a wavefront whose spectra converge
+// quickly takes more of them.  The start point is evaluated
 // as a trial from the same centre and width with zero depth (where r = y - b
 // and g = 0 hold exactly), so one loop body serves both.  A wave exits when
-// its chunk is exhausted and all its groups are idle; every fit is bounded by
-// max_iter.
+// the block's range is exhausted and all its groups are idle; every fit is
+// bounded by max_iter.
 //
 // Schedule (the paper fixes only the cap and the tolerance): lam0 = 1e-3,
 // /10 on accept, *10 on reject; accept when finite, width > 0 and chi2 does
@@ -224,8 +227,10 @@ __device__ __forceinline__ float resolution_floor(int k, double b0) {
   return (float)k * s * s;
 }
 
+constexpr int LM_WAVES = 8;  // wavefronts per block
+
 template <int G, int Q>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void lm_kernel(
+__global__ __launch_bounds__(64 * LM_WAVES) __attribute__((amdgpu_waves_per_eu(2, 8))) void lm_kernel(
     const float* __restrict__ y, const float* __restrict__ p0, const int32_t* __restrict__ idx,
     const int32_t* __restrict__ count, int64_t nf, int k, int max_iter, int chunk,
     float* __restrict__ params, int32_t* __restrict__ iters, int32_t* __restrict__ status,
@@ -234,21 +239,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   // a counter the next kernel on the stream accumulates into (the fallback
   // list after a polish), cleared here so that no kernel has to do only that
   if (zero_count && blockIdx.x == 0 && threadIdx.x == 0) *zero_count = 0;
+  __shared__ int s_next;  // next unclaimed spectrum of the block's range (offset)
   const int lane = lane_id();
   const int grp = lane / G;
   const int gl = lane & (G - 1);
-  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t base = wave * chunk;
+  const int wv = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * LM_WAVES * chunk;
   int64_t n = nf;
   if (count) {
     const int64_t c = *count;
     n = c < nf ? (c < 0 ? 0 : c) : nf;
   }
-  if (base >= n) return;
-  const int64_t end = base + chunk < n ? base + chunk : n;
+  if (base >= n) return;  // uniform over the block
+  const int64_t span = (int64_t)LM_WAVES * chunk;
+  const int64_t end = base + span < n ? base + span : n;
+  if (threadIdx.x == 0) s_next = LM_WAVES * NG;
+  __syncthreads();  // the only block barrier
 
-  int64_t s = base + grp;  // spectrum of this group (>= end: idle)
-  int64_t next = base + NG;  // wave-uniform hand-out index
+  int64_t s = base + wv * NG + grp;  // spectrum of this group (>= end: idle)
   bool active = s < end;
   bool fresh = true;
   float r[Q], g[Q], rn[Q], gn[Q];
@@ -349,9 +357,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     }
     const uint64_t fin = __ballot(done && gl == 0);
     if (fin != 0ull) {
+      // reserve one spectrum per finished group from the block's range
+      int off = 0;
+      if (lane == 0) off = atomicAdd(&s_next, (int)__popcll(fin));
+      off = __shfl(off, 0);
       if (done) {
         const uint64_t below = fin & ((1ull << (grp * G)) - 1ull);
-        s = next + __popcll(below);
+        s = base + off + __popcll(below);
         active = s < end;
         fresh = true;
         if (active) {
@@ -367,7 +379,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
           ue = -c * ua;
         }
       }
-      next += __popcll(fin);
     }
   }
 }
@@ -467,10 +478,10 @@ hipError_t launch_lm_gq(const float* y, const float* p0, const int32_t* idx,
                         const int32_t* count, int64_t nf, int k, int max_iter, int chunk,
                         float* params, int32_t* iters, int32_t* status, float* chi2,
                         int32_t status_code, int32_t* zero_count, hipStream_t s) {
-  const int64_t waves = (nf + chunk - 1) / chunk;
-  const int64_t blocks = (waves + 3) / 4;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((lm_kernel<G, Q>), dim3((unsigned)blocks), dim3(256), 0, s, y, p0, idx,
+  const int64_t span = (int64_t)LM_WAVES * chunk;  // spectra per block
+  const int64_t blocks = (nf + span - 1) / span;
+  if (blocks > 0x7fffffff || span > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((lm_kernel<G, Q>), dim3((unsigned)blocks), dim3(64 * LM_WAVES), 0, s, y, p0, idx,
                      count, nf, k, max_iter, chunk, params, iters, status, chi2, status_code,
                      zero_count);
   return hipGetLastError();
