@@ -14,8 +14,11 @@
 // averages.
 //
 // gfx950 layout: as the Lorentzian fit (lm.hip) -- a group of G lanes per
-// spectrum (8 up to 224 teeth, else 16), 64/G spectra per wavefront, lane gl
-// owns teeth gl + G q; model, residual and chi2 per tooth in FP64, the three
+// spectrum (8 up to 224 teeth, else 16), 64/G spectra per wavefront, a
+// block's eight wavefronts sharing its range of spectra through an LDS
+// counter, lane gl owns teeth gl + G q; model, residual and chi2 per tooth in
+// FP64 (the fit has one free positional parameter and no width change, so
+// the Lorentzian fit's differential FP32 form would save nothing here), the three
 // Jacobian columns and the nine normal-equation sums in FP32 with their
 // per-spectrum factors applied to the reduced sums, DPP reductions giving
 // bit-identical sums in every lane of a group, and the damped 3x3 system
@@ -171,28 +174,33 @@ __device__ __forceinline__ double clampd(double v, double lo, double hi) {
 // A wave fits a contiguous chunk of spectra; groups that finish take the next
 // spectrum of the chunk (wave-uniform hand-out index), as in the Lorentzian
 // fit.  Start point: p0[f][0] as the centre, d and b at their averages.
+constexpr int FANO_WAVES = 8;  // wavefronts per block (they share the block's range)
+
 template <int G, int Q>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void fano_kernel(
+__global__ __launch_bounds__(64 * FANO_WAVES) __attribute__((amdgpu_waves_per_eu(3, 8))) void fano_kernel(
     const float* __restrict__ y, const float* __restrict__ p0, int64_t nf, int k, int max_iter,
     int chunk, FanoArgs fa, float* __restrict__ params, int32_t* __restrict__ iters,
     int32_t* __restrict__ status, float* __restrict__ chi2_out,
     const int32_t* __restrict__ dev_n) {
   constexpr int NG = 64 / G;
+  __shared__ int s_next;  // next unclaimed spectrum of the block's range (offset)
   const int lane = lane_id();
   const int grp = lane / G;
   const int gl = lane & (G - 1);
-  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t base = wave * chunk;
+  const int wv = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * FANO_WAVES * chunk;
   int64_t n = nf;
   if (dev_n) {
     const int64_t dn = *dev_n;
     n = dn < nf ? (dn < 0 ? 0 : dn) : nf;
   }
-  if (base >= n) return;
-  const int64_t end = base + chunk < n ? base + chunk : n;
+  if (base >= n) return;  // uniform over the block
+  const int64_t span = (int64_t)FANO_WAVES * chunk;
+  const int64_t end = base + span < n ? base + span : n;
+  if (threadIdx.x == 0) s_next = FANO_WAVES * NG;
+  __syncthreads();  // the only block barrier
 
-  int64_t s = base + grp;
-  int64_t next = base + NG;
+  int64_t s = base + wv * NG + grp;
   bool active = s < end;
   bool fresh = true;
   float yv[Q];
@@ -259,9 +267,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     }
     const uint64_t fin = __ballot(done && gl == 0);
     if (fin != 0ull) {
+      // one spectrum per finished group from the block's range
+      int off = 0;
+      if (lane == 0) off = atomicAdd(&s_next, (int)__popcll(fin));
+      off = __shfl(off, 0);
       if (done) {
         const uint64_t below = fin & ((1ull << (grp * G)) - 1ull);
-        s = next + __popcll(below);
+        s = base + off + __popcll(below);
         active = s < end;
         fresh = true;
         d = d_start;
@@ -271,7 +283,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
           c = p0[s * 4 + 0];
         }
       }
-      next += __popcll(fin);
     }
   }
 }
@@ -280,10 +291,10 @@ template <int G, int Q>
 hipError_t launch_fano_gq(const float* y, const float* p0, int64_t nf, int k, int max_iter,
                           int chunk, const FanoArgs& fa, float* params, int32_t* iters,
                           int32_t* status, float* chi2, hipStream_t s, const int32_t* dev_n) {
-  const int64_t waves = (nf + chunk - 1) / chunk;
-  const int64_t blocks = (waves + 3) / 4;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fano_kernel<G, Q>), dim3((unsigned)blocks), dim3(256), 0, s, y, p0, nf, k,
+  const int64_t span = (int64_t)FANO_WAVES * chunk;  // spectra per block
+  const int64_t blocks = (nf + span - 1) / span;
+  if (blocks > 0x7fffffff || span > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fano_kernel<G, Q>), dim3((unsigned)blocks), dim3(64 * FANO_WAVES), 0, s, y, p0, nf, k,
                      max_iter, chunk, fa, params, iters, status, chi2, dev_n);
   return hipGetLastError();
 }
