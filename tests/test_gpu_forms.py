@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from parity_util import PASS_FRACTION, centre_parity, mag_rel_err
+from parity_util import MAG_RTOL, PASS_FRACTION, centre_parity, mag_rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -68,6 +68,34 @@ def test_mfma_whole_path_centres(form):
                         ora["chi2"])
     _say(f"{form}: centre fraction {res['fraction']:.5f} max_err {res['max_err']:.2e}")
     assert res["fraction"] >= PASS_FRACTION, res
+
+
+def test_precision_full_size_sampled():
+    """The precision workload at its full size and launch shape (131072 frames
+    x 4096 int16, 220 teeth, one launch per form): every 61st frame and the
+    last one against the FP64 oracle, at each form's bars (the FFT at 1e-4)."""
+    spec = synth.spec_precision()
+    bt = synth.make_batch(spec, 16384, seed=2)
+    frames = np.tile(bt.frames, (8, 1))                 # 131072 frames
+    nf = frames.shape[0]
+    ref = oracle.reference_spectrum(bt.ref_frames, spec.bins).astype(np.float32)
+    plan = cg.Plan(spec.n, spec.fs, spec.bins, ref)
+    sample = np.unique(np.concatenate([np.arange(0, nf, 61), [nf - 1]]))
+    m_or = oracle.tooth_magnitudes(frames[sample], spec.bins)
+    fr = torch.from_numpy(frames).to(DEV)
+    forms = {"fft": (cg.DFT_FFT, MAG_RTOL, MAG_RTOL)}
+    forms.update(FORMS)
+    for name, (flag, max_bar, rms_bar) in forms.items():
+        _say(f"precision full size: {name}")
+        mag, _ = plan.teeth(fr, flags=flag, want_y=False)
+        torch.cuda.synchronize()
+        err = mag_rel_err(mag[torch.from_numpy(sample).to(DEV)].cpu().numpy(), m_or)
+        _say(f"  {len(sample)} sampled frames: max {err.max():.2e} rms "
+             f"{np.sqrt(np.mean(err ** 2)):.2e}")
+        assert err.max() <= max_bar
+        assert np.sqrt(np.mean(err ** 2)) <= rms_bar
+        del mag
+    plan.close()
 
 
 def test_mfma_rejects_misaligned_frames():

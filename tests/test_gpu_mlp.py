@@ -229,6 +229,41 @@ def test_warm_path_with_trained_network():
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not built")
+def test_warm_path_full_batch_sampled():
+    """The learned warm start at the benchmark's size and launch shape (65536
+    frames x 2048 int16, one launch of the whole warm path: network, polish,
+    fallback list, cold refits): a contiguous 2048-frame stretch in the middle
+    of the batch against the oracle's warm path on that stretch, away from
+    its ends (the oracle's 7x7 median replicates the stretch's edge frames
+    where the GPU sees their neighbours)."""
+    d = np.load(WEIGHTS)
+    spec = synth.spec_learned()
+    bt = synth.make_batch(spec, 65536, seed=1)
+    ref = oracle.reference_spectrum(bt.ref_frames, spec.bins).astype(np.float32)
+    plan = cg.Plan(spec.n, spec.fs, spec.bins, ref)
+    plan.set_mlp(d["params"], d["out_mean"], d["out_std"], float(d["noise_floor"]))
+    _say("warm full batch: GPU")
+    warm = plan.process(torch.from_numpy(bt.frames).to(DEV), flags=cg.FIT_WARM_MLP,
+                        want=("params", "status"))
+    torch.cuda.synchronize()
+    a, b = 30000, 32048
+    _say("warm full batch: oracle on the stretch")
+    ora = oracle.pipeline.process_batch_warm(bt.frames[a:b], spec.bins, ref,
+                                             d["params"].astype(np.float64), d["out_mean"],
+                                             d["out_std"], float(d["noise_floor"]))
+    inner = slice(3, b - a - 3)
+    gp = warm["params"].cpu().numpy()[a:b][inner]
+    gs = warm["status"].cpu().numpy()[a:b][inner]
+    res = centre_parity(ora["y"][inner], gp, ora["params"][inner],
+                        warm_compared(ora["status"][inner]), ora["chi2"][inner])
+    _say(f"  fallback gpu {np.mean(warm['status'].cpu().numpy() == 3):.4f} (batch), "
+         f"stretch gpu {np.mean(gs == 3):.4f} oracle {np.mean(ora['status'][inner] == 3):.4f}; "
+         f"parity {res['fraction']:.5f} of {res['n']}")
+    assert res["fraction"] >= PASS_FRACTION, res
+    assert np.mean(gs == ora["status"][inner]) >= 0.99
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not built")
 def test_warm_path_polish_to_convergence():
     """With the polish run to the cold start's cap the warm form is a full LM
     fit from the network's start point: parity with the oracle's warm form at
