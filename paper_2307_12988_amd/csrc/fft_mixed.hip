@@ -17,8 +17,9 @@
 // pairwise form (sums and differences of v_r and v_{R-r} against cos and
 // sin), about a quarter of the multiplies of the plain DFT.
 //
-// gfx950 layout: one wavefront per frame.  A persistent block of four
-// wavefronts shares the W_1100 table in LDS; each wavefront owns one 1100-
+// gfx950 layout: one wavefront per frame.  A persistent block of wavefronts
+// (four, or eight in the comb shape below) shares the W_1100 table in LDS;
+// each wavefront owns one 1100-
 // point complex buffer in LDS and walks its own frames (stride: every
 // wavefront of the grid), keeping the next frame's raw words in registers
 // while the current one is transformed (non-temporal loads).  The raw words
@@ -42,8 +43,6 @@ namespace {
 
 constexpr int MX_M = 1100;        // complex points
 constexpr int MX_N = 2 * MX_M;    // samples per frame
-constexpr int MX_THREADS = 256;
-constexpr int MX_WAVES = MX_THREADS / 64;
 
 struct cx {
   float x, y;
@@ -212,11 +211,27 @@ __device__ __forceinline__ void first_pass(cx* z, int lane) {
   wave_sync();
 }
 
-constexpr size_t mx_lds_bytes() { return (size_t)(MX_WAVES + 1) * MX_M * sizeof(cx); }
+// Launch shapes: rounds of 64 butterflies a lane may run in the last three
+// passes (R1, R2, R3) and wavefronts per block.  The general shape covers any
+// tooth set; the comb shape covers tooth sets whose pruned passes need at
+// most 2, 1 and 1 rounds (the paper's comb): its smaller register arrays let
+// four wavefronts share a SIMD, and eight-wavefront blocks share one twiddle
+// table in LDS.
+struct ShapeGeneral {
+  static constexpr int R1 = 4, R2 = 4, R3 = 2, WAVES = 4;
+};
+struct ShapeComb {
+  static constexpr int R1 = 2, R2 = 1, R3 = 1, WAVES = 8;
+};
+
+template <class SH>
+constexpr size_t mx_lds_bytes() {
+  return (size_t)(SH::WAVES + 1) * MX_M * sizeof(cx);
+}
 
 // TR = rounds of 64 teeth a lane covers (k <= 64 TR).
-template <typename T, int TR>
-__global__ __launch_bounds__(MX_THREADS) void fft_mixed_kernel(
+template <typename T, int TR, class SH>
+__global__ __launch_bounds__(64 * SH::WAVES) void fft_mixed_kernel(
     const T* __restrict__ frames, int64_t n_frames, const int32_t* __restrict__ bins,
     const float* __restrict__ half_inv_ref, const cx* __restrict__ tw_m,
     const cx* __restrict__ tw_tooth, int k, const int16_t* __restrict__ lists, int nr1, int nr2,
@@ -230,8 +245,9 @@ __global__ __launch_bounds__(MX_THREADS) void fft_mixed_kernel(
     const int64_t dn = *dev_n;
     n_frames = dn < n_frames ? dn : n_frames;
   }
-  if ((int64_t)blockIdx.x * MX_WAVES >= n_frames) return;  // uniform over the block
-  for (int e = threadIdx.x; e < MX_M; e += MX_THREADS) tw[e] = tw_m[e];
+  constexpr int WAVES = SH::WAVES;
+  if ((int64_t)blockIdx.x * WAVES >= n_frames) return;  // uniform over the block
+  for (int e = threadIdx.x; e < MX_M; e += 64 * WAVES) tw[e] = tw_m[e];
   // this lane's teeth: i = lane + 64 q
   int lo[TR], hi[TR];
   cx tt[TR];
@@ -246,19 +262,19 @@ __global__ __launch_bounds__(MX_THREADS) void fft_mixed_kernel(
     thr[q] = i < k ? half_inv_ref[i] : 0.f;
   }
   // this lane's butterflies in the last three passes
-  int j1[4], j2[4], j3[2];
+  int j1[SH::R1], j2[SH::R2], j3[SH::R3];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) j1[q] = q < nr1 ? lists[64 * q + lane] : -1;
+  for (int q = 0; q < SH::R1; ++q) j1[q] = q < nr1 ? lists[64 * q + lane] : -1;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) j2[q] = q < nr2 ? lists[64 * (nr1 + q) + lane] : -1;
+  for (int q = 0; q < SH::R2; ++q) j2[q] = q < nr2 ? lists[64 * (nr1 + q) + lane] : -1;
 #pragma unroll
-  for (int q = 0; q < 2; ++q) j3[q] = q < nr3 ? lists[64 * (nr1 + nr2 + q) + lane] : -1;
+  for (int q = 0; q < SH::R3; ++q) j3[q] = q < nr3 ? lists[64 * (nr1 + nr2 + q) + lane] : -1;
   __syncthreads();  // the twiddle table; no block barrier after this
   using RW = Raw<T>;
   constexpr int WPL = (RW::WORDS + 63) / 64;  // raw words per lane
   const int32_t* words = reinterpret_cast<const int32_t*>(frames);
-  const int64_t stride = (int64_t)gridDim.x * MX_WAVES;
-  int64_t f = (int64_t)blockIdx.x * MX_WAVES + wv;
+  const int64_t stride = (int64_t)gridDim.x * WAVES;
+  int64_t f = (int64_t)blockIdx.x * WAVES + wv;
   int32_t raw[WPL];
   auto fetch = [&](int64_t fr) __attribute__((always_inline)) {
 #pragma unroll
@@ -280,9 +296,9 @@ __global__ __launch_bounds__(MX_THREADS) void fft_mixed_kernel(
     if (f + stride < n_frames) fetch(f + stride);  // next frame in flight
     wave_sync();
     first_pass<T>(z, lane);
-    pass<5, 4, 4>(z, tw, j1, nr1);
-    pass<5, 20, 4>(z, tw, j2, nr2);
-    pass<11, 100, 2>(z, tw, j3, nr3);
+    pass<5, 4, SH::R1>(z, tw, j1, nr1);
+    pass<5, 20, SH::R2>(z, tw, j2, nr2);
+    pass<11, 100, SH::R3>(z, tw, j3, nr3);
     // epilogue: 2 X[b] = (Z[b] + conj Z[M-b]) - i W_N^b (Z[b] - conj Z[M-b])
 #pragma unroll
     for (int q = 0; q < TR; ++q) {
@@ -304,11 +320,12 @@ __global__ __launch_bounds__(MX_THREADS) void fft_mixed_kernel(
   }
 }
 
-template <typename T, int TR>
+template <typename T, int TR, class SH>
 int mx_grid_limit_t(const cg_plan* p) {
   int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fft_mixed_kernel<T, TR>, MX_THREADS,
-                                                   mx_lds_bytes()) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fft_mixed_kernel<T, TR, SH>,
+                                                   64 * SH::WAVES,
+                                                   mx_lds_bytes<SH>()) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
           hipSuccess ||
       per_cu <= 0 || cus <= 0)
@@ -316,15 +333,16 @@ int mx_grid_limit_t(const cg_plan* p) {
   return per_cu * cus;
 }
 
-template <typename T, int TR>
+template <typename T, int TR, class SH>
 hipError_t launch_mx_t(const cg_plan* p, const void* frames, int64_t nf, float* out_mag,
                        float* out_y, hipStream_t s, const int32_t* dev_n) {
-  int64_t blocks = (nf + MX_WAVES - 1) / MX_WAVES;
+  int64_t blocks = (nf + SH::WAVES - 1) / SH::WAVES;
   if (p->fft_blocks > 0 && blocks > p->fft_blocks) blocks = p->fft_blocks;
   if (p->fft_cap > 0 && blocks > p->fft_cap) blocks = p->fft_cap;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   if (blocks == 0) return hipSuccess;
-  fft_mixed_kernel<T, TR><<<dim3((unsigned)blocks), dim3(MX_THREADS), mx_lds_bytes(), s>>>(
+  fft_mixed_kernel<T, TR, SH><<<dim3((unsigned)blocks), dim3(64 * SH::WAVES),
+                                mx_lds_bytes<SH>(), s>>>(
       static_cast<const T*>(frames), nf, p->d_bins, p->d_half_inv_ref,
       reinterpret_cast<const cx*>(p->d_tw_mixed), reinterpret_cast<const cx*>(p->d_tooth_w),
       p->k, p->d_mx_list, p->mx_rounds[0], p->mx_rounds[1], p->mx_rounds[2], out_mag, out_y,
@@ -332,34 +350,53 @@ hipError_t launch_mx_t(const cg_plan* p, const void* frames, int64_t nf, float* 
   return hipGetLastError();
 }
 
-// One instantiation per tooth rounds (k <= CG_MAX_TEETH = 440: up to 7).
+// The comb shape when the plan's pruned passes fit it.
+bool comb_shape(const cg_plan* p) {
+  return p->mx_rounds[0] <= ShapeComb::R1 && p->mx_rounds[1] <= ShapeComb::R2 &&
+         p->mx_rounds[2] <= ShapeComb::R3;
+}
+
+// One instantiation per tooth rounds (k <= CG_MAX_TEETH = 440: up to 7) and
+// launch shape.
+template <typename T, class SH>
+int mx_grid_limit_s(const cg_plan* p) {
+  switch ((p->k + 63) / 64) {
+    case 1: return mx_grid_limit_t<T, 1, SH>(p);
+    case 2: return mx_grid_limit_t<T, 2, SH>(p);
+    case 3: return mx_grid_limit_t<T, 3, SH>(p);
+    case 4: return mx_grid_limit_t<T, 4, SH>(p);
+    case 5: return mx_grid_limit_t<T, 5, SH>(p);
+    case 6: return mx_grid_limit_t<T, 6, SH>(p);
+    case 7: return mx_grid_limit_t<T, 7, SH>(p);
+    default: return 0;
+  }
+}
+
 template <typename T>
 int mx_grid_limit(const cg_plan* p) {
+  return comb_shape(p) ? mx_grid_limit_s<T, ShapeComb>(p) : mx_grid_limit_s<T, ShapeGeneral>(p);
+}
+
+template <typename T, class SH>
+hipError_t launch_mx_s(const cg_plan* p, const void* frames, int64_t nf, float* out_mag,
+                       float* out_y, hipStream_t s, const int32_t* dev_n) {
   switch ((p->k + 63) / 64) {
-    case 1: return mx_grid_limit_t<T, 1>(p);
-    case 2: return mx_grid_limit_t<T, 2>(p);
-    case 3: return mx_grid_limit_t<T, 3>(p);
-    case 4: return mx_grid_limit_t<T, 4>(p);
-    case 5: return mx_grid_limit_t<T, 5>(p);
-    case 6: return mx_grid_limit_t<T, 6>(p);
-    case 7: return mx_grid_limit_t<T, 7>(p);
-    default: return 0;
+    case 1: return launch_mx_t<T, 1, SH>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 2: return launch_mx_t<T, 2, SH>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 3: return launch_mx_t<T, 3, SH>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 4: return launch_mx_t<T, 4, SH>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 5: return launch_mx_t<T, 5, SH>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 6: return launch_mx_t<T, 6, SH>(p, frames, nf, out_mag, out_y, s, dev_n);
+    case 7: return launch_mx_t<T, 7, SH>(p, frames, nf, out_mag, out_y, s, dev_n);
+    default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
 hipError_t launch_mx(const cg_plan* p, const void* frames, int64_t nf, float* out_mag,
                      float* out_y, hipStream_t s, const int32_t* dev_n) {
-  switch ((p->k + 63) / 64) {
-    case 1: return launch_mx_t<T, 1>(p, frames, nf, out_mag, out_y, s, dev_n);
-    case 2: return launch_mx_t<T, 2>(p, frames, nf, out_mag, out_y, s, dev_n);
-    case 3: return launch_mx_t<T, 3>(p, frames, nf, out_mag, out_y, s, dev_n);
-    case 4: return launch_mx_t<T, 4>(p, frames, nf, out_mag, out_y, s, dev_n);
-    case 5: return launch_mx_t<T, 5>(p, frames, nf, out_mag, out_y, s, dev_n);
-    case 6: return launch_mx_t<T, 6>(p, frames, nf, out_mag, out_y, s, dev_n);
-    case 7: return launch_mx_t<T, 7>(p, frames, nf, out_mag, out_y, s, dev_n);
-    default: return hipErrorInvalidValue;
-  }
+  return comb_shape(p) ? launch_mx_s<T, ShapeComb>(p, frames, nf, out_mag, out_y, s, dev_n)
+                       : launch_mx_s<T, ShapeGeneral>(p, frames, nf, out_mag, out_y, s, dev_n);
 }
 
 }  // namespace
