@@ -245,6 +245,13 @@ cg_status cg_create_plan_ex(int32_t frame_len, double fs, const int32_t* tooth_b
   CG_TRY(cg::resolve_static_scratch(p->device), "fixed scratch: hipGetSymbolAddress");
 #undef CG_TRY
   p->fft_blocks = cg::fft_grid_limit(p);
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) ==
+            hipSuccess &&
+        cus > 0)
+      cg::set_compute_units(cus);
+  }
   *out_plan = p;
   return CG_OK;
 }

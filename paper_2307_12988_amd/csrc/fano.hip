@@ -174,7 +174,7 @@ __device__ __forceinline__ double clampd(double v, double lo, double hi) {
 // A wave fits a contiguous chunk of spectra; groups that finish take the next
 // spectrum of the chunk (wave-uniform hand-out index), as in the Lorentzian
 // fit.  Start point: p0[f][0] as the centre, d and b at their averages.
-constexpr int FANO_WAVES = 8;  // wavefronts per block (they share the block's range)
+constexpr int FANO_WAVES = 8;  // most wavefronts per block (they share the block's range)
 
 template <int G, int Q>
 __global__ __launch_bounds__(64 * FANO_WAVES) __attribute__((amdgpu_waves_per_eu(3, 8))) void fano_kernel(
@@ -188,16 +188,17 @@ __global__ __launch_bounds__(64 * FANO_WAVES) __attribute__((amdgpu_waves_per_eu
   const int grp = lane / G;
   const int gl = lane & (G - 1);
   const int wv = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * FANO_WAVES * chunk;
+  const int nw = (int)(blockDim.x >> 6);  // wavefronts in this block
+  const int64_t base = (int64_t)blockIdx.x * nw * chunk;
   int64_t n = nf;
   if (dev_n) {
     const int64_t dn = *dev_n;
     n = dn < nf ? (dn < 0 ? 0 : dn) : nf;
   }
   if (base >= n) return;  // uniform over the block
-  const int64_t span = (int64_t)FANO_WAVES * chunk;
+  const int64_t span = (int64_t)nw * chunk;
   const int64_t end = base + span < n ? base + span : n;
-  if (threadIdx.x == 0) s_next = FANO_WAVES * NG;
+  if (threadIdx.x == 0) s_next = nw * NG;
   __syncthreads();  // the only block barrier
 
   int64_t s = base + wv * NG + grp;
@@ -291,10 +292,11 @@ template <int G, int Q>
 hipError_t launch_fano_gq(const float* y, const float* p0, int64_t nf, int k, int max_iter,
                           int chunk, const FanoArgs& fa, float* params, int32_t* iters,
                           int32_t* status, float* chi2, hipStream_t s, const int32_t* dev_n) {
-  const int64_t span = (int64_t)FANO_WAVES * chunk;  // spectra per block
+  const int nw = fit_waves_per_block((nf + chunk - 1) / chunk);
+  const int64_t span = (int64_t)nw * chunk;  // spectra per block
   const int64_t blocks = (nf + span - 1) / span;
   if (blocks > 0x7fffffff || span > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fano_kernel<G, Q>), dim3((unsigned)blocks), dim3(64 * FANO_WAVES), 0, s, y, p0, nf, k,
+  hipLaunchKernelGGL((fano_kernel<G, Q>), dim3((unsigned)blocks), dim3(64 * nw), 0, s, y, p0, nf, k,
                      max_iter, chunk, fa, params, iters, status, chi2, dev_n);
   return hipGetLastError();
 }

@@ -110,6 +110,11 @@ hipError_t launch_start_points(const float* m, int64_t n_frames, int k, float* o
 // (<= 0: chosen from n_frames and the tooth count).
 // lanes = lanes per spectrum (8 or 16; 0: 8 up to 224 teeth, else 16).
 int lm_group(int n_teeth);
+// Compute units of the device (sizes the fit kernels' blocks; set at plan
+// creation).
+void set_compute_units(int cus);
+// Wavefronts per block (1 .. 8) of a fit launch of `waves` wavefronts.
+int fit_waves_per_block(int64_t waves);
 int lm_chunk(int64_t n_frames, int n_teeth, int lanes = 0);
 // zero_count, if not null, is set to 0 by the kernel (for a counter the next
 // kernel on the stream accumulates into).

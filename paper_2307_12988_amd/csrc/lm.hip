@@ -50,6 +50,8 @@
 // not increase; converged when an accepted step lowers chi2 by at most
 // 1e-6 * chi2_old or chi2 <= 1e-30 (or at the FP32 resolution floor below);
 // a non-positive-definite damped matrix stops the fit as singular.
+#include <atomic>
+
 #include "fp64.h"
 #include "internal.h"
 #include "wave.h"
@@ -227,7 +229,7 @@ __device__ __forceinline__ float resolution_floor(int k, double b0) {
   return (float)k * s * s;
 }
 
-constexpr int LM_WAVES = 8;  // wavefronts per block
+constexpr int LM_WAVES = 8;  // most wavefronts per block
 
 template <int G, int Q>
 __global__ __launch_bounds__(64 * LM_WAVES) __attribute__((amdgpu_waves_per_eu(2, 8))) void lm_kernel(
@@ -244,16 +246,17 @@ __global__ __launch_bounds__(64 * LM_WAVES) __attribute__((amdgpu_waves_per_eu(2
   const int grp = lane / G;
   const int gl = lane & (G - 1);
   const int wv = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * LM_WAVES * chunk;
+  const int nw = (int)(blockDim.x >> 6);  // wavefronts in this block (1 .. LM_WAVES)
+  const int64_t base = (int64_t)blockIdx.x * nw * chunk;
   int64_t n = nf;
   if (count) {
     const int64_t c = *count;
     n = c < nf ? (c < 0 ? 0 : c) : nf;
   }
   if (base >= n) return;  // uniform over the block
-  const int64_t span = (int64_t)LM_WAVES * chunk;
+  const int64_t span = (int64_t)nw * chunk;
   const int64_t end = base + span < n ? base + span : n;
-  if (threadIdx.x == 0) s_next = LM_WAVES * NG;
+  if (threadIdx.x == 0) s_next = nw * NG;
   __syncthreads();  // the only block barrier
 
   int64_t s = base + wv * NG + grp;  // spectrum of this group (>= end: idle)
@@ -473,15 +476,21 @@ int lm_chunk(int64_t nf, int k, int lanes) {
 
 namespace {
 
+// Compute units of the device plans were last created on (set at plan
+// creation, read at launch: launches may be captured into graphs, where no
+// device query is made).
+std::atomic<int> g_compute_units{0};
+
 template <int G, int Q>
 hipError_t launch_lm_gq(const float* y, const float* p0, const int32_t* idx,
                         const int32_t* count, int64_t nf, int k, int max_iter, int chunk,
                         float* params, int32_t* iters, int32_t* status, float* chi2,
                         int32_t status_code, int32_t* zero_count, hipStream_t s) {
-  const int64_t span = (int64_t)LM_WAVES * chunk;  // spectra per block
+  const int nw = fit_waves_per_block((nf + chunk - 1) / chunk);
+  const int64_t span = (int64_t)nw * chunk;  // spectra per block
   const int64_t blocks = (nf + span - 1) / span;
   if (blocks > 0x7fffffff || span > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((lm_kernel<G, Q>), dim3((unsigned)blocks), dim3(64 * LM_WAVES), 0, s, y, p0, idx,
+  hipLaunchKernelGGL((lm_kernel<G, Q>), dim3((unsigned)blocks), dim3(64 * nw), 0, s, y, p0, idx,
                      count, nf, k, max_iter, chunk, params, iters, status, chi2, status_code,
                      zero_count);
   return hipGetLastError();
@@ -527,6 +536,21 @@ hipError_t launch_lm_any(const float* y, const float* p0, const int32_t* idx,
 }
 
 }  // namespace
+
+void set_compute_units(int cus) { g_compute_units.store(cus, std::memory_order_relaxed); }
+
+// Wavefronts per block for a launch of `waves` wavefronts: the block's
+// wavefronts share its range of spectra, so blocks are as large as allowed
+// while every compute unit still gets a block; small launches use smaller
+// blocks spread over more compute units.
+int fit_waves_per_block(int64_t waves) {
+  const int c = g_compute_units.load(std::memory_order_relaxed);
+  const int cus = c > 0 ? c : 256;
+  int nw = 8;
+  while (nw > 1 && waves < (int64_t)nw * cus) nw >>= 1;
+  return nw;
+}
+
 
 hipError_t launch_lm(const float* y, const float* p0, int64_t nf, int k, int max_iter,
                      float* params, int32_t* iters, int32_t* status, float* chi2, hipStream_t s,
