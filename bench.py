@@ -53,7 +53,7 @@ TRAFFIC = {
     "fft_teeth": (("fft_teeth.hip",), "2f0f3ebdc945fa9a", 131307.4 * 2 * 1024, 56323.4 * 1024),
     "median_start": (("median.hip", "wave.h"), "1ac469519e98187a", 39067.4 * 2 * 1024,
                      1024.0 * 1024),
-    "lm_fit": (("lm.hip", "wave.h", "fp64.h"), "a259e784d9494191", 28756.0 * 2 * 1024,
+    "lm_fit": (("lm.hip", "wave.h", "fp64.h"), "10b4d8aba4c5537a", 28756.0 * 2 * 1024,
                1559.9 * 1024),
 }
 

@@ -15,7 +15,7 @@
 //
 // gfx950 layout: as the Lorentzian fit (lm.hip) -- a group of G lanes per
 // spectrum (8 up to 224 teeth, else 16), 64/G spectra per wavefront, a
-// block's eight wavefronts sharing its range of spectra through an LDS
+// block's (up to eight) wavefronts sharing its range of spectra through an LDS
 // counter, lane gl owns teeth gl + G q; model, residual and chi2 per tooth in
 // FP64 (the fit has one free positional parameter and no width change, so
 // the Lorentzian fit's differential FP32 form would save nothing here), the three

@@ -32,8 +32,9 @@
 // sums.  Evaluating a trial point also produces the normal equations there,
 // so an accepted step needs no second pass.
 //
-// A block of eight wavefronts owns a contiguous range of spectra (eight
-// chunks).  The LM loop body is the same for every iteration, so groups run
+// A block of up to eight wavefronts (fewer for small launches, so that
+// every compute unit gets a block) owns a contiguous range of spectra (one
+// chunk per wavefront).  The LM loop body is the same for every iteration, so groups run
 // independent fits in lock step: when a group finishes it writes its result
 // and takes the next spectrum of the block's range (a wavefront reserves as
 // many as it has finished groups with one LDS atomic add), evaluates the new
