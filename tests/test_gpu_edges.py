@@ -1,0 +1,130 @@
+"""Degenerate batch sizes through every fit form: empty batches, single
+frames and batches shorter than the 7x7 median window (the window then
+replicates the batch's edge frames on both sides), against the FP64 oracle
+on the same frames."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.pipeline
+import synth
+from parity_util import MAG_RTOL, PASS_FRACTION, centre_parity, mag_rel_err, warm_compared
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2307_12988_amd as cg  # noqa: E402
+from test_gpu_fano import fano_parity  # noqa: E402
+
+DEV = torch.device("cuda:0")
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2307_12988_amd", "data", "warmstart_learned.npz")
+W, Q, DBAR, BBAR = 8.03, 4.0, 0.6, 1.0
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("nf", [1, 2, 3, 6, 7, 8])
+def test_short_batches_cold_path(nf):
+    """Fewer frames than (or as many as) the median window: amplitudes, start
+    points (bit-identical on the same spectra) and centres."""
+    spec = synth.spec_tiny()
+    bt = synth.make_batch(spec, nf, seed=40 + nf)
+    ref = oracle.reference_spectrum(bt.ref_frames, spec.bins).astype(np.float32)
+    ora = oracle.process_batch(bt.frames, spec.bins, ref)
+    plan = cg.Plan(spec.n, spec.fs, spec.bins, ref)
+    out = plan.process(torch.from_numpy(bt.frames).to(DEV),
+                       want=("params", "status", "teeth", "y"))
+    torch.cuda.synchronize()
+    assert mag_rel_err(out["teeth"].cpu().numpy(), ora["mags"]).max() <= MAG_RTOL
+    y = out["y"]
+    p0_gpu, med = plan.init_spectra(y, want_median=True)
+    torch.cuda.synchronize()
+    y_np = y.cpu().numpy()
+    assert np.array_equal(med.cpu().numpy(), oracle.median7x7(y_np))
+    assert np.array_equal(p0_gpu.cpu().numpy(), oracle.initial_guess(y_np))
+    res = centre_parity(ora["y"], out["params"].cpu().numpy(), ora["params"], ora["status"],
+                        ora["chi2"])
+    _say(f"nf={nf}: centres {res['fraction']:.3f} of {res['n']}, max {res['max_err']:.2e}")
+    assert res["fraction"] >= PASS_FRACTION, res
+
+
+@pytest.mark.parametrize("nf", [0, 1, 3, 5])
+def test_short_batches_paper_configuration(nf):
+    """The paper's 8-bit 2200-sample frames with the boxed Fano fit."""
+    spec = synth.spec_paper8()
+    bt = synth.make_batch(spec, max(nf, 1), seed=60 + nf)
+    frames = bt.frames[:nf]
+    ref = oracle.reference_spectrum(bt.ref_frames, spec.bins).astype(np.float32)
+    plan = cg.Plan(spec.n, spec.fs, spec.bins, ref, sample_type="int8")
+    plan.set_fano(W, Q, DBAR, BBAR)
+    out = plan.process(torch.from_numpy(np.ascontiguousarray(frames)).to(DEV),
+                       flags=cg.FIT_FANO, want=("params", "status", "teeth"))
+    torch.cuda.synchronize()
+    assert out["params"].shape == (nf, 4)
+    if nf == 0:
+        return
+    ora = oracle.pipeline.process_batch_fano(frames, spec.bins, ref, W, Q, DBAR, BBAR)
+    assert mag_rel_err(out["teeth"].cpu().numpy(), ora["mags"]).max() <= MAG_RTOL
+    res = fano_parity(ora["y"], out["params"].cpu().numpy(), ora["params"], ora["status"],
+                      ora["chi2"], W, Q)
+    _say(f"paper8 nf={nf}: centres {res['fraction']:.3f} of {res['n']}")
+    assert res["fraction"] >= PASS_FRACTION, res
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not built")
+@pytest.mark.parametrize("nf", [0, 1, 4])
+def test_short_batches_warm_path(nf):
+    """The learned warm start (network, polish, fallback, refit) on tiny
+    batches."""
+    d = np.load(WEIGHTS)
+    spec = synth.spec_learned()
+    bt = synth.make_batch(spec, max(nf, 1), seed=80 + nf)
+    frames = np.ascontiguousarray(bt.frames[:nf])
+    ref = oracle.reference_spectrum(bt.ref_frames, spec.bins).astype(np.float32)
+    plan = cg.Plan(spec.n, spec.fs, spec.bins, ref)
+    plan.set_mlp(d["params"], d["out_mean"], d["out_std"], float(d["noise_floor"]))
+    out = plan.process(torch.from_numpy(frames).to(DEV), flags=cg.FIT_WARM_MLP,
+                       want=("params", "status"))
+    torch.cuda.synchronize()
+    assert out["params"].shape == (nf, 4)
+    if nf == 0:
+        return
+    ora = oracle.pipeline.process_batch_warm(frames, spec.bins, ref,
+                                             d["params"].astype(np.float64), d["out_mean"],
+                                             d["out_std"], float(d["noise_floor"]))
+    assert np.array_equal(out["status"].cpu().numpy() == 3, ora["status"] == 3)
+    res = centre_parity(ora["y"], out["params"].cpu().numpy(), ora["params"],
+                        warm_compared(ora["status"]), ora["chi2"])
+    _say(f"warm nf={nf}: centres {res['fraction']:.3f} of {res['n']}")
+    assert res["fraction"] >= PASS_FRACTION, res
+
+
+@pytest.mark.parametrize("flag", [cg.DFT_MFMA_BF16X3, cg.DFT_MFMA_FP16X2, cg.DFT_MFMA_FP16])
+@pytest.mark.parametrize("nf", [0, 1, 17])
+def test_short_batches_matrix_core_forms(flag, nf):
+    """The matrix-core tooth transforms on batches smaller than one tile of
+    frames (an empty batch writes nothing)."""
+    spec = synth.spec_precision()
+    bt = synth.make_batch(spec, max(nf, 1), seed=90 + nf)
+    frames = np.ascontiguousarray(bt.frames[:nf])
+    plan = cg.Plan(spec.n, spec.fs, spec.bins, np.ones(spec.k, np.float32))
+    mag, _ = plan.teeth(torch.from_numpy(frames).to(DEV), flags=flag, want_y=False)
+    torch.cuda.synchronize()
+    assert mag.shape == (nf, spec.k)
+    if nf == 0:
+        return
+    bar = {cg.DFT_MFMA_BF16X3: 1e-4, cg.DFT_MFMA_FP16X2: 1e-3, cg.DFT_MFMA_FP16: 3e-3}[flag]
+    err = mag_rel_err(mag.cpu().numpy(), oracle.tooth_magnitudes(frames, spec.bins))
+    assert err.max() <= bar
