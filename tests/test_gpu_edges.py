@@ -128,3 +128,31 @@ def test_short_batches_matrix_core_forms(flag, nf):
     bar = {cg.DFT_MFMA_BF16X3: 1e-4, cg.DFT_MFMA_FP16X2: 1e-3, cg.DFT_MFMA_FP16: 3e-3}[flag]
     err = mag_rel_err(mag.cpu().numpy(), oracle.tooth_magnitudes(frames, spec.bins))
     assert err.max() <= bar
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_fewer_teeth_than_parameters(k):
+    """One to three teeth for a four-parameter dip.  One tooth: the damped
+    normal matrix has a zero column (no tooth sees the width or the centre
+    move), and both sides report every fit singular.  Two or three teeth: the
+    dip can pass through every tooth, so fits are not unique and their
+    iteration counts depend on rounding; only the outcome is checked: a
+    valid status, and a final chi2 no larger than at the start point."""
+    spec = synth.StreamSpec(name="few", n=512, fs=1e9, bins=np.arange(10, 10 + 5 * k, 5),
+                            width=(4, 16), snr_db=(30, 50))
+    bt = synth.make_batch(spec, 40, seed=k)
+    ref = oracle.reference_spectrum(bt.ref_frames, spec.bins).astype(np.float32)
+    ora = oracle.process_batch(bt.frames, spec.bins, ref)
+    plan = cg.Plan(spec.n, spec.fs, spec.bins, ref)
+    out = plan.process(torch.from_numpy(bt.frames).to(DEV), want=("params", "status", "y"))
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    if k == 1:
+        assert np.all(st == cg.FIT_SINGULAR) and np.all(ora["status"] == 2)
+        return
+    assert np.all(np.isin(st, (0, 1, 2)))
+    y = out["y"].cpu().numpy().astype(np.float64)
+    p = out["params"].cpu().numpy()
+    p0 = oracle.initial_guess(out["y"].cpu().numpy())
+    for f in np.nonzero(st != 2)[0]:
+        assert oracle.chi2_at(y[f], p[f]) <= oracle.chi2_at(y[f], p0[f]) * (1 + 1e-5) + 1e-12
