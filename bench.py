@@ -481,8 +481,9 @@ def fano_workload(args, torch, cg, dev):
         plan.teeth(pool[rot[0] % len(pool)], want_mag=False, want_y=True, out_y=y)
 
     plan.teeth(pool[0], want_mag=False, want_y=True, out_y=y)
+    # the Fano fit starts from the median centres alone (the path's own form)
     launch = {"fft_teeth": fft_launch,
-              "median_start": lambda: plan.init_spectra(y, out_p0=p0),
+              "median_start": lambda: plan.start_centres(y, out_p0=p0),
               "fano_fit": lambda: plan.fit_fano(y, p0, out=fit_out)}
     plan.init_spectra(y, out_p0=p0)
     reps = max(3, min(args.steps, 10))

@@ -261,6 +261,17 @@ cg_status cg_init_spectra_listed(cg_plan* plan, const float* y, int64_t n_frames
                                  const int32_t* listed, float* out_p0, void* stream);
 
 /*
+ * The start centres alone (paper, Data Capture and Processing: the lowest
+ * value of each row of the 7x7-median image): column 0 of out_p0 (device
+ * float32 [n_frames][4]) receives the same centre cg_init_spectra writes;
+ * columns 1..3 are left untouched.  The boxed Fano fit starts from these
+ * (its extent and scale start at the plan's averages).  Errors as for
+ * cg_init_spectra.
+ */
+cg_status cg_start_centres(cg_plan* plan, const float* y, int64_t n_frames, float* out_p0,
+                           void* stream);
+
+/*
  * The two kernels of cg_init_spectra, callable on their own:
  * cg_median_filter writes out_median = 7x7 median image of y (both device
  * float32 [n_frames][n_teeth], distinct buffers); cg_start_points turns a

@@ -41,6 +41,7 @@ SIGNATURES = {
     "cg_reference_from_frames": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_init_spectra": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "cg_init_spectra_listed": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
+    "cg_start_centres": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_median_filter": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_start_points": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "cg_fit_spectra": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp]),

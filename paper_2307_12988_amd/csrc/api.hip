@@ -407,7 +407,9 @@ cg_status process_impl(cg_plan* p, const void* frames, int64_t nf, float* out_pa
     if (e != hipSuccess) return hip_fail(e, "warm-start launch");
     return CG_OK;
   }
-  e = cg::launch_median_start(y, nf, p->k, nullptr, p0, s);
+  // the Fano fit starts from the median centre alone
+  e = cg::launch_median_start(y, nf, p->k, nullptr, p0, s, nullptr, nullptr,
+                              fit == CG_FIT_FANO);
   if (e != hipSuccess) return hip_fail(e, "median/start launch");
   if (fit == CG_FIT_FANO) {
     e = cg::launch_fano(p, y, p0, nf, 20, out_params, out_iters, out_status, out_chi2, s);
@@ -481,6 +483,17 @@ cg_status cg_init_spectra(cg_plan* p, const float* y, int64_t nf, float* out_p0,
   if (y == out_median) return CG_ERR_INVALID_ARG;
   hipError_t e = cg::launch_median_start(y, nf, p->k, out_median, out_p0, cg::pick(p, stream));
   if (e != hipSuccess) return hip_fail(e, "init launch");
+  return CG_OK;
+}
+
+cg_status cg_start_centres(cg_plan* p, const float* y, int64_t nf, float* out_p0, void* stream) {
+  if (!p || !out_p0) return CG_ERR_NULL;
+  if (nf < 0) return CG_ERR_INVALID_ARG;
+  if (nf == 0) return CG_OK;
+  if (!y) return CG_ERR_NULL;
+  hipError_t e = cg::launch_median_start(y, nf, p->k, nullptr, out_p0, cg::pick(p, stream),
+                                         nullptr, nullptr, true);
+  if (e != hipSuccess) return hip_fail(e, "start centres launch");
   return CG_OK;
 }
 

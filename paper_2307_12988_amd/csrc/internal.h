@@ -99,9 +99,11 @@ hipError_t launch_column_mean(const float* mags, int64_t n, int k, float* out, h
 // flags (may be null): only frames with flags[f] != 0 get a start point (and
 // a filtered row in out_m; rows of other frames are left unwritten), and
 // blocks without such frames return at once.
+// centre_only: only p0[f][0] (the start centre) is written (the Fano fit's
+// start; needs flags == nullptr).
 hipError_t launch_median_start(const float* y, int64_t n_frames, int k, float* out_m,
                                float* out_p0, hipStream_t s, const int32_t* flags = nullptr,
-                               const int32_t* dev_n = nullptr);
+                               const int32_t* dev_n = nullptr, bool centre_only = false);
 // Start points from a given median image.
 hipError_t launch_start_points(const float* m, int64_t n_frames, int k, float* out_p0,
                                hipStream_t s);

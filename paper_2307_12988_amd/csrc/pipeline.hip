@@ -257,7 +257,8 @@ hipError_t capture_slot(const PipeStream& ps, PipeSlot& sl, int cap) {
                              sl.iters, sl.status, sl.chi2, CG_FIT_FALLBACK, s);
   } else {
     if (le == hipSuccess)
-      le = launch_median_start(sl.y, cap, p->k, nullptr, sl.p0, s, nullptr, sl.n_dev);
+      le = launch_median_start(sl.y, cap, p->k, nullptr, sl.p0, s, nullptr, sl.n_dev,
+                               (ps.flags & CG_FIT_MASK) == CG_FIT_FANO);
     if (le == hipSuccess && (ps.flags & CG_FIT_MASK) == CG_FIT_FANO)
       le = launch_fano(p, sl.y, sl.p0, cap, 20, sl.params, sl.iters, sl.status, sl.chi2, s,
                        sl.n_dev);

@@ -164,6 +164,23 @@ __device__ __forceinline__ int count_below16(const uint32_t (&keys)[Q], uint32_t
 //   w0 = max(2, #{M < b0 (1 - d0/2)}).
 // The arithmetic that decides d0 and the count uses IEEE float32 operations in
 // that order (no contraction), so identical inputs give identical results.
+// The start centre alone: the first index of the smallest filtered value,
+// as start_point16 finds it (same keys, same tie rule).
+template <int Q>
+__device__ __forceinline__ float start_centre16(const float (&mv)[Q]) {
+  const int gl = lane_id() & 15;
+  uint32_t bk = 0xffffffffu, bi = 0u;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const uint32_t key = float_key(mv[q] + 0.0f);  // -0 -> +0
+    const bool lt = key < bk || q == 0;
+    bk = lt ? key : bk;
+    bi = lt ? (uint32_t)(gl + 16 * q) : bi;
+  }
+  const uint64_t best = min16(((uint64_t)bk << 32) | bi);
+  return (float)(int)(uint32_t)best;
+}
+
 template <int Q>
 __device__ __forceinline__ void start_point16(const float (&mv)[Q], int k, float& c0, float& w0,
                                               float& d0, float& b0) {

@@ -239,6 +239,18 @@ class Plan:
         _lib.check(st, "cg_init_spectra")
         return p0, med
 
+    def start_centres(self, y, out_p0=None):
+        """The 7x7-median start centres alone (column 0 of out_p0 [n, 4]; the
+        other columns are left as they are): the Fano fit's start."""
+        nf = int(y.shape[0])
+        if out_p0 is None:
+            out_p0 = torch.zeros((nf, 4), dtype=torch.float32, device=y.device)
+        yp = _dev_ptr(y, torch.float32, (nf, self.n_teeth), "y")
+        pp = _dev_ptr(out_p0, torch.float32, (nf, 4), "p0")
+        st = self._lib.cg_start_centres(self._h, yp, nf, pp, _stream(y.device))
+        _lib.check(st, "cg_start_centres")
+        return out_p0
+
     def init_spectra_listed(self, y, listed, out_p0):
         """Start points for the frames with listed[f] != 0 (int32 device
         tensor); the other rows of out_p0 are left as they are."""

@@ -156,3 +156,21 @@ def test_fewer_teeth_than_parameters(k):
     p0 = oracle.initial_guess(out["y"].cpu().numpy())
     for f in np.nonzero(st != 2)[0]:
         assert oracle.chi2_at(y[f], p[f]) <= oracle.chi2_at(y[f], p0[f]) * (1 + 1e-5) + 1e-12
+
+
+@pytest.mark.parametrize("k,nf", [(220, 1000), (100, 37), (440, 70), (7, 20)])
+def test_start_centres_equal_full_start_points(k, nf):
+    """cg_start_centres writes the centre cg_init_spectra writes (column 0)
+    and leaves the other columns alone."""
+    rng = np.random.default_rng(k + nf)
+    y = (1.0 - 0.5 * rng.random((nf, k))).astype(np.float32)
+    plan = cg.Plan(2048, 1e9, np.arange(1, k + 1), np.ones(k))
+    yt = torch.from_numpy(y).to(DEV)
+    p0, _ = plan.init_spectra(yt)
+    c = torch.full((nf, 4), -3.0, dtype=torch.float32, device=DEV)
+    plan.start_centres(yt, out_p0=c)
+    torch.cuda.synchronize()
+    c = c.cpu().numpy()
+    assert np.array_equal(c[:, 0], p0.cpu().numpy()[:, 0])
+    assert np.all(c[:, 1:] == -3.0)
+    assert np.array_equal(c[:, 0], oracle.initial_guess(y)[:, 0])
