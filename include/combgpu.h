@@ -265,8 +265,11 @@ cg_status cg_init_spectra_listed(cg_plan* plan, const float* y, int64_t n_frames
  * value of each row of the 7x7-median image): column 0 of out_p0 (device
  * float32 [n_frames][4]) receives the same centre cg_init_spectra writes;
  * columns 1..3 are left untouched.  The boxed Fano fit starts from these
- * (its extent and scale start at the plan's averages).  Errors as for
- * cg_init_spectra.
+ * (its extent and scale start at the plan's averages).  Only the columns
+ * whose window bounds (smallest and largest median of a window's row
+ * segments) leave room for a row's minimum are filtered exactly, so spectra
+ * with a dip take less time than cg_init_spectra; the centres are the same.
+ * Errors as for cg_init_spectra.
  */
 cg_status cg_start_centres(cg_plan* plan, const float* y, int64_t n_frames, float* out_p0,
                            void* stream);

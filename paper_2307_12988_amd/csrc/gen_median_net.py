@@ -32,7 +32,10 @@ the two-input ones, so two further rewrites pay:
   the other four one at a time; inserting x into a sorted list s gives
   min(x, s0), med3(s(j-1), x, s(j)) for the inner positions and
   max(x, s_last): 25 operations instead of the 32 of the best two-input
-  network (16 comparators).
+  network (16 comparators).  CG_MED7 keeps only the operations that the
+  4th smallest needs (13 instructions): the bounds of the centre-only
+  start, where a window's median lies between the smallest and the largest
+  median of its seven row segments.
 * In a pruned merge, max(min(a, b), c) equals med3(a, b, c) whenever c <= a
   or c <= b holds for every input, and min(max(a, b), c) does whenever
   a <= c or b <= c does; where the inner operation has no other use the two
@@ -208,6 +211,19 @@ def sort7_ops():
     return ops, s
 
 
+def med7_ops():
+    """The 4th smallest of V[0..6]: sort7_ops without the operations that
+    output does not depend on."""
+    ops, outs = sort7_ops()
+    live = {outs[3]}
+    kept = []
+    for op in reversed(ops):
+        if op[0] in live:
+            kept.append(op)
+            live.update(op[2:])
+    return kept[::-1], [outs[3]]
+
+
 def emit(name, kept, outs, n_in, in_name="IN", out_name="OUT"):
     lines = [f"// {name}: {len(kept)} min/max/med3 operations",
              f"#define {name}({in_name}, {out_name}) do {{ \\"]
@@ -235,6 +251,8 @@ def main(path):
     s7, s7o = sort7_ops()
     zo = np.array([[(bits >> i) & 1 for i in range(7)] for bits in range(128)], dtype=np.int8)
     assert np.array_equal(evaluate(s7, s7o, zo), np.sort(zo, axis=1))
+    m7, m7o = med7_ops()
+    assert np.array_equal(evaluate(m7, m7o, zo)[:, 0], np.sort(zo, axis=1)[:, 3])
     nets = {}
     for name, lens, ranks in (("k77", [7, 7], list(range(14))),
                               ("kc", [14, 14], list(range(3, 25))),
@@ -263,6 +281,7 @@ def main(path):
             assert np.array_equal(got, want), (trial, w)
     text = ["// Generated by gen_median_net.py -- do not edit.", ""]
     text.append(emit_sort7("CG_SORT7"))
+    text.append(emit("CG_MED7", m7, m7o, 7, "V", "OUT"))
     text.append(emit("CG_MERGE77", k77, o77, 14))
     text.append(emit("CG_CORE_R3_24", kc, oc, 28))
     text.append(emit("CG_PAIR_R14_21", kp, op, 36))

@@ -100,7 +100,8 @@ hipError_t launch_column_mean(const float* mags, int64_t n, int k, float* out, h
 // a filtered row in out_m; rows of other frames are left unwritten), and
 // blocks without such frames return at once.
 // centre_only: only p0[f][0] (the start centre) is written (the Fano fit's
-// start; needs flags == nullptr).
+// start; needs out_p0 and no flags or out_m: the median image is computed
+// exactly only where a row's minimum can lie).
 hipError_t launch_median_start(const float* y, int64_t n_frames, int k, float* out_m,
                                float* out_p0, hipStream_t s, const int32_t* flags = nullptr,
                                const int32_t* dev_n = nullptr, bool centre_only = false);

@@ -5,6 +5,7 @@ on the same frames."""
 
 import os
 import sys
+import zlib
 
 import numpy as np
 import pytest
@@ -156,6 +157,92 @@ def test_fewer_teeth_than_parameters(k):
     p0 = oracle.initial_guess(out["y"].cpu().numpy())
     for f in np.nonzero(st != 2)[0]:
         assert oracle.chi2_at(y[f], p[f]) <= oracle.chi2_at(y[f], p0[f]) * (1 + 1e-5) + 1e-12
+
+
+def _dip_rows(nf, k, rng, centre, depth=0.6, width=8.0, noise=0.02, step=None):
+    """Lorentzian dips at the given centres (one per frame) plus Gaussian
+    noise, optionally rounded to multiples of `step` (many equal values)."""
+    x = np.arange(k)
+    y = 1.0 - depth / (1.0 + (2.0 * (x[None, :] - centre[:, None]) / width) ** 2)
+    y = y + noise * rng.standard_normal((nf, k))
+    if step:
+        y = np.round(y / step) * step
+    return y.astype(np.float32)
+
+
+def _centre_case(case, k, nf, rng):
+    t = np.arange(nf)
+    mid = (k - 1) / 2
+    if case == "dip":            # the stream's motion: +-10 teeth at 1/42 of the frame rate
+        return _dip_rows(nf, k, rng, mid + min(10.0, k / 4) * np.sin(2 * np.pi * t / 42.0))
+    if case == "dip_low_edge":   # minima on and next to the first tooth
+        return _dip_rows(nf, k, rng, 1.5 + 1.5 * np.sin(2 * np.pi * t / 13.0))
+    if case == "dip_high_edge":
+        return _dip_rows(nf, k, rng, k - 2.5 + 1.5 * np.sin(2 * np.pi * t / 13.0))
+    if case == "noisy":          # the bounds overlap widely: most columns are filtered
+        return _dip_rows(nf, k, rng, mid + 0 * t, depth=0.05, noise=0.05)
+    if case == "quantised":      # equal values everywhere, bounds equal to u
+        return _dip_rows(nf, k, rng, mid + 6.0 * np.sin(2 * np.pi * t / 29.0), noise=0.05,
+                         step=1 / 16)
+    if case == "two_equal_dips":  # two identical minima per row: the first one counts
+        prof = 1.0 - 0.6 / (1.0 + (2.0 * (np.arange(k) - k // 4) / 6.0) ** 2)
+        row = np.minimum(prof, prof[::-1]).astype(np.float32)
+        return np.repeat(row[None, :], nf, axis=0)
+    if case == "flat":
+        return np.ones((nf, k), np.float32)
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case,k,nf", [
+    ("dip", 220, 2000), ("dip", 100, 333), ("dip", 440, 300), ("dip", 7, 50),
+    ("dip_low_edge", 220, 500), ("dip_high_edge", 220, 500), ("dip_high_edge", 61, 100),
+    ("noisy", 220, 500), ("quantised", 220, 1000), ("quantised", 33, 77),
+    ("two_equal_dips", 220, 64), ("two_equal_dips", 40, 17), ("flat", 220, 40), ("flat", 1, 5)])
+def test_start_centres_pruned_filter_cases(case, k, nf):
+    """The centre-only kernel filters exactly only the columns whose window
+    bounds (the smallest and largest median of the window's seven row
+    segments) leave room for a row's minimum.  These cases put the minimum on
+    the edge teeth, tie it between columns, make values equal to the bounds
+    and flatten the rows, so that the bounds keep few, many or all columns;
+    every centre must be the oracle's (first index of the filtered row's
+    minimum) and the full start-point kernel's."""
+    rng = np.random.default_rng(zlib.crc32(f"{case} {k} {nf}".encode()))
+    y = _centre_case(case, k, nf, rng)
+    plan = cg.Plan(2048, 1e9, np.arange(1, k + 1), np.ones(k))
+    yt = torch.from_numpy(y).to(DEV)
+    c = torch.full((nf, 4), -3.0, dtype=torch.float32, device=DEV)
+    plan.start_centres(yt, out_p0=c)
+    p0, _ = plan.init_spectra(yt)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy()[:, 0]
+    want = oracle.initial_guess(y)[:, 0]
+    bad = np.nonzero(got != want)[0]
+    _say(f"{case} k={k} nf={nf}: {len(bad)} centres differ from the oracle"
+         + (f", first frame {bad[0]}: {got[bad[0]]} vs {want[bad[0]]}" if len(bad) else ""))
+    assert len(bad) == 0
+    assert np.array_equal(got, p0.cpu().numpy()[:, 0])
+    if case == "two_equal_dips":
+        # the filtered row is flat at its minimum over five teeth in each
+        # dip: the first of those ten equal values counts
+        assert np.all(got == k // 4 - 2)
+
+
+def test_start_centres_on_the_fano_stream():
+    """Start centres of the Fano stream's spectra (the GPU path's own y) equal
+    the oracle's on the same spectra."""
+    spec = synth.spec_fano()
+    bt = synth.make_batch(spec, 1500, seed=77)
+    plan = cg.Plan(spec.n, spec.fs, spec.bins, np.ones(spec.k, dtype=np.float32))
+    ref = plan.reference_from_frames(torch.from_numpy(bt.ref_frames).to(DEV)).cpu().numpy()
+    plan.set_reference(ref)
+    _, y = plan.teeth(torch.from_numpy(bt.frames).to(DEV), want_mag=False, want_y=True)
+    c = torch.zeros((1500, 4), dtype=torch.float32, device=DEV)
+    plan.start_centres(y, out_p0=c)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy()[:, 0]
+    want = oracle.initial_guess(y.cpu().numpy())[:, 0]
+    _say(f"Fano stream: {np.sum(got != want)} of 1500 centres differ")
+    assert np.array_equal(got, want)
 
 
 @pytest.mark.parametrize("k,nf", [(220, 1000), (100, 37), (440, 70), (7, 20)])

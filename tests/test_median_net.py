@@ -36,6 +36,26 @@ def test_row_sort_sorts_every_input_with_ties():
     assert len(ops) == 27  # 25 instructions once min(min()) and max(max()) fuse
 
 
+def test_row_median_is_the_fourth_smallest_with_ties():
+    g = _gen()
+    ops, outs = g.med7_ops()
+    rng = np.random.default_rng(5)
+    for v in (rng.integers(0, 4, size=(50000, 7)).astype(np.float64), rng.random((50000, 7))):
+        assert np.array_equal(g.evaluate(ops, outs, v)[:, 0], np.sort(v, axis=1)[:, 3])
+    assert len(ops) == 15  # 13 instructions once min(min()) and max(max()) fuse
+
+
+def test_window_median_lies_between_its_row_medians():
+    """The bound the centre-only start relies on: a 7x7 window's median is
+    at least the smallest and at most the largest median of its rows."""
+    rng = np.random.default_rng(6)
+    for v in (rng.integers(0, 3, size=(20000, 7, 7)).astype(np.float64),
+              rng.random((20000, 7, 7)) ** 3):
+        med = np.sort(v.reshape(-1, 49), axis=1)[:, 24]
+        rows = np.sort(v, axis=2)[:, :, 3]
+        assert np.all(rows.min(axis=1) <= med) and np.all(med <= rows.max(axis=1))
+
+
 def test_med3_rewrite_keeps_the_merge_and_saves_operations():
     g = _gen()
     for lens, ranks in (([22, 14], list(range(14, 22))), ([14, 14], list(range(3, 25))),
