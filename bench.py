@@ -50,11 +50,11 @@ SEED = 1
 # for the kernel sources they were taken on:
 # kernel -> (sources, sha256 prefix of their concatenation, read B, write B)
 TRAFFIC = {
-    "fft_teeth": (("fft_teeth.hip",), "2f0f3ebdc945fa9a", 131307.4 * 2 * 1024, 56323.4 * 1024),
-    "median_start": (("median.hip", "wave.h"), "1ac469519e98187a", 39067.4 * 2 * 1024,
+    "fft_teeth": (("fft_teeth.hip",), "2f0f3ebdc945fa9a", 131296.5 * 2 * 1024, 56324.6 * 1024),
+    "median_start": (("median.hip", "wave.h"), "4307231e62d2b61b", 39064.4 * 2 * 1024,
                      1024.0 * 1024),
-    "lm_fit": (("lm.hip", "wave.h", "fp64.h"), "10b4d8aba4c5537a", 28756.0 * 2 * 1024,
-               1559.9 * 1024),
+    "lm_fit": (("lm.hip", "wave.h", "fp64.h"), "51d796c9d72c5864", 28756.0 * 2 * 1024,
+               1036.3 * 1024),
 }
 
 
@@ -1099,6 +1099,15 @@ def main():
             plan.process(pool[i % len(pool)], params=outs[j][0], iters=outs[j][1],
                          status=outs[j][2], workspace=wss[j], want=())
 
+    # the plan's launch shape, tuned on one batch of the pool (as a user would
+    # once per plan); the tuner runs the path for some 100 ms before it times
+    # candidates, since an idle device starts at a low clock
+    t0 = time.perf_counter()
+    _, tune_ms = plan.autotune(pool[0])
+    tuned = {**plan.tuned_shape(), "ms_per_batch_one_stream": tune_ms,
+             "tuner_s": time.perf_counter() - t0}
+    _log(f"autotune: {tuned}")
+
     _log("warmup ...")
     for i in range(args.warmup):
         step(i)
@@ -1245,7 +1254,7 @@ def main():
                                f"batch, {k} teeth, cold-start 7x7 median + LM (<=20 it)",
                    "frames_per_batch": nf, "frame_len": n, "n_teeth": k,
                    "pool_batches": args.pool, "pool_GiB": args.pool * nf * n * 2 / 2 ** 30,
-                   "streams": ns},
+                   "streams": ns, "launch_shape": tuned},
         "spectra_per_s": sps,
         "fit": {"mean_iters": float(it_np.mean()), "converged_frac": float(np.mean(st_np == 0)),
                 "status_counts": np.bincount(st_np, minlength=4).tolist()},

@@ -525,7 +525,12 @@ cg_status cg_pipeline_stats(cg_pipeline* pipe, double* out, int32_t n_out);
  * x FFT grid (every resident block, half of them) -- installs the fastest in
  * the plan (read it back with cg_get_tuning) and returns its spectra per
  * wavefront (*chosen) and its time per batch (*best_ms, may be NULL).
- * Synchronises the device; allocates a parameter buffer for the timing.
+ * Timing: the plan's current shape first runs for at least 100 ms of device
+ * time (an idle device starts at a low clock that rises over its first
+ * milliseconds of work), then every candidate is timed once per round over
+ * three rounds and keeps its fastest time; a timing covers passes over about
+ * 64 Ki frames (at most 16 passes).  Synchronises the device; allocates a
+ * parameter buffer for the timing.
  */
 cg_status cg_autotune(cg_plan* plan, const void* frames, int64_t n_frames, uint32_t flags,
                       void* workspace, size_t workspace_bytes, int32_t* chosen, float* best_ms);
