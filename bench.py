@@ -453,6 +453,13 @@ def fano_workload(args, torch, cg, dev):
             plan.process(pool[i % len(pool)], params=outs[j][0], iters=outs[j][1],
                          status=outs[j][2], workspace=wss[j], flags=cg.FIT_FANO, want=())
 
+    # the launch shape tuned on one batch, as for the paper-rate workload
+    t0 = time.perf_counter()
+    _, tune_ms = plan.autotune(pool[0], flags=cg.FIT_FANO)
+    tuned = {**plan.tuned_shape(), "ms_per_batch_one_stream": tune_ms,
+             "tuner_s": time.perf_counter() - t0}
+    _log(f"autotune: {tuned}")
+
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize(dev)
@@ -521,7 +528,7 @@ def fano_workload(args, torch, cg, dev):
                                    f"{FANO_Q} fixed, extent and scale boxed +-10% of {FANO_DBAR} "
                                    f"and {FANO_BBAR}",
                        "frames_per_batch": nf, "frame_len": n, "n_teeth": k,
-                       "pool_batches": args.pool, "streams": ns},
+                       "pool_batches": args.pool, "streams": ns, "launch_shape": tuned},
             "spectra_per_s": nf * args.steps / wall,
             "fit": {"mean_iters": float(it_np.mean()),
                     "status_counts": np.bincount(st_np, minlength=3).tolist()},
