@@ -529,7 +529,8 @@ cg_status cg_pipeline_stats(cg_pipeline* pipe, double* out, int32_t n_out);
  * time (an idle device starts at a low clock that rises over its first
  * milliseconds of work), then every candidate is timed once per round over
  * three rounds and keeps its fastest time; a timing covers passes over about
- * 64 Ki frames (at most 16 passes).  Synchronises the device; allocates a
+ * 64 Ki frames (at most 16 passes).  The plan's current shape is kept unless
+ * a candidate is at least 3 % faster.  Synchronises the device; allocates a
  * parameter buffer for the timing.
  */
 cg_status cg_autotune(cg_plan* plan, const void* frames, int64_t n_frames, uint32_t flags,

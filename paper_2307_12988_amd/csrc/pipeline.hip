@@ -796,7 +796,11 @@ cg_status cg_autotune(cg_plan* p, const void* frames, int64_t nf, uint32_t flags
   struct Shape {
     int lanes, chunk, fft;
   };
-  std::vector<Shape> cands;
+  // candidate 0 is the plan's current shape (0 = automatic choice), which
+  // another candidate replaces only when it is at least 3 % faster: shapes
+  // within the run-to-run spread of a timing would otherwise be picked by it
+  const int32_t saved[3] = {p->lm_lanes, p->lm_chunk, p->fft_cap};
+  std::vector<Shape> cands{Shape{saved[0], saved[1], saved[2]}};
   const int lane_opts[] = {8, 16};
   const int chunk_mult[] = {1, 2, 4, 8};
   const int fft_opts[] = {0, p->fft_blocks > 1 ? p->fft_blocks / 2 : 0};
@@ -819,7 +823,6 @@ cg_status cg_autotune(cg_plan* p, const void* frames, int64_t nf, uint32_t flags
     (void)hipFree(params);
     return hip_fail(e, "autotune events");
   }
-  const int32_t saved[3] = {p->lm_lanes, p->lm_chunk, p->fft_cap};
   auto run = [&]() {
     return cg_process_batch_ex(p, frames, nf, params, nullptr, nullptr, nullptr, nullptr, nullptr,
                                flags, workspace, workspace_bytes, nullptr);
@@ -857,10 +860,10 @@ cg_status cg_autotune(cg_plan* p, const void* frames, int64_t nf, uint32_t flags
       if (st != CG_OK) break;
       fastest[ci] = std::min(fastest[ci], elapsed() / (float)reps);
     }
-  float best = 1e30f;
-  Shape pick = {saved[0], saved[1], saved[2]};
-  for (size_t ci = 0; ci < cands.size(); ++ci)
-    if (fastest[ci] < best) {
+  float best = fastest[0];
+  Shape pick = cands[0];
+  for (size_t ci = 1; ci < cands.size(); ++ci)
+    if (fastest[ci] < 0.97f * fastest[0] && fastest[ci] < best) {
       best = fastest[ci];
       pick = cands[ci];
     }
@@ -876,7 +879,10 @@ cg_status cg_autotune(cg_plan* p, const void* frames, int64_t nf, uint32_t flags
   p->lm_lanes = pick.lanes;
   p->lm_chunk = pick.chunk;
   p->fft_cap = pick.fft;
-  *chosen = pick.chunk;
+  // the spectra per wavefront the fit uses (the automatic choice resolved)
+  *chosen = pick.chunk > 0
+                ? pick.chunk
+                : cg::lm_chunk(nf, p->k, pick.lanes > 0 ? pick.lanes : cg::lm_group(p->k));
   if (best_ms) *best_ms = best;
   return CG_OK;
 }

@@ -5,7 +5,7 @@ bursts of streams with different frame lengths, tooth counts and fit forms.
 * The sixteen-stream configuration with the trained warm start matches the
   FP64 oracle's warm path on a 1-in-16 sample of every burst at the plain
   path's centre bar (>= 99.9 % within 1e-3 FWHM).
-* The autotuner installs one of its candidate shapes, and results stay at
+* The autotuner keeps the plan's own shape or installs one of its candidate shapes, and results stay at
   the bar whatever shape it picks."""
 
 import os
@@ -156,10 +156,16 @@ def test_autotune_picks_a_candidate():
     chunk, ms = pl.autotune(fr)
     shape = pl.tuned_shape()
     _say(f"autotune: {shape}, {ms:.3f} ms")
-    assert shape["lm_lanes"] in (8, 16) and chunk == shape["lm_chunk"] and ms > 0
-    assert chunk in (8, 16, 32, 64) if shape["lm_lanes"] == 8 else chunk in (4, 8, 16, 32)
+    assert ms > 0
+    # the plan's own (automatic) shape stays unless a candidate is 3 % faster
+    auto = shape == {"lm_lanes": 0, "lm_chunk": 0, "fft_blocks": 0}
+    if auto:
+        assert chunk in (8, 16, 32, 64)  # the automatic chunk, resolved (8 lanes at 220 teeth)
+    else:
+        assert shape["lm_lanes"] in (8, 16) and chunk == shape["lm_chunk"]
+        assert chunk in (8, 16, 32, 64) if shape["lm_lanes"] == 8 else chunk in (4, 8, 16, 32)
     again = pl.process(fr, want=("params",))["params"].cpu().numpy()
-    if shape["lm_lanes"] == 8:
+    if auto or shape["lm_lanes"] == 8:
         # the default shape for 220 teeth: only the order of work changed
         assert np.array_equal(base, again)
     # whatever the shape, the centres stay at the bar against the oracle
