@@ -317,8 +317,10 @@ cg_status cg_fit_spectra(cg_plan* plan, const float* y, const float* p0, int64_t
  * parameter on a bound whose gradient points out of the box is held for the
  * step and every trial point is clipped into the box.  Start point: the
  * centre of the 7x7-median initializer (cg_init_spectra), extent and scale
- * at their averages.  Schedule and statuses as the Lorentzian fit.  Output
- * parameters (centre, width (the fixed value), extent, scale).
+ * at their averages.  Schedule, statuses and arithmetic as the Lorentzian
+ * fit (FP32 per tooth, the chi2 decrease of a step from the model's change,
+ * the same resolution floor; FP64 Cholesky).  Output parameters (centre,
+ * width (the fixed value), extent, scale).
  * cg_set_fano: width > 0, |asymmetry| >= 1e-3, averages > 0, all finite
  * (host doubles; CG_ERR_INVALID_ARG otherwise).  cg_fit_fano: the fit alone
  * on normalised spectra y (device float32 [n_frames][n_teeth]) from start
